@@ -1,0 +1,147 @@
+/*
+ * gwr.h -- C ABI of the space-time polarizability / self-energy library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the atom-pair-blocked real-space, imaginary-time
+ * forms of the polarizability P (Eq. (5), MT-MT) and of the self-energy
+ * Sigma (Eq. (8), MT-MT) of Kutepov's O(N) self-consistent GW method, and the
+ * lattice (k <-> R) and Matsubara (tau -> i omega) transforms that feed and
+ * drain them (Sec. 2: the F^R_{rr'} storage, the R <-> k transforms whose
+ * cost is proportional to the number of pairs).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A cell has n_atoms atoms; atom A has species s(A), n_orb[s] orbitals and
+ *    n_pb[s] product functions.  Orbitals and product functions occupy
+ *    contiguous index ranges in atom order; N_orb and N_pb are their totals.
+ *  - The Born-von Karman mesh N1 x N2 x N3 gives N_R = N_k = N1*N2*N3.  R and k
+ *    are indexed (n1 * N2 + n2) * N3 + n3 with 0 <= n_i < N_i;
+ *    k.R = 2 pi sum_i j_i n_i / N_i.  -R is taken modulo the mesh.
+ *  - F^R_ab = F(a in cell R, b in cell 0);  F(k) = sum_R exp(-i k.R) F^R;
+ *    F^R = N_k^-1 sum_k exp(+i k.R) F(k).
+ *  - tau_i, i = 0 .. n_tau-1, is a grid on [0, beta] that is symmetric about
+ *    beta/2; tau_0 stands for 0+ and tau_{n_tau-1} for beta-, and the mirror
+ *    beta - tau_i is the index n_tau-1-i.
+ *  - Tensors are dense, row-major and contiguous, complex numbers stored
+ *    interleaved (re, im):
+ *        G, Sigma  [n_tau][N_R][N_orb][N_orb]     ("orbital basis", basis = 0)
+ *        P, W      [n_tau][N_R][N_pb][N_pb]       ("product basis", basis = 1)
+ *    After a transform the leading axis may be frequency and the second k.
+ *  - Every tensor pointer is a DEVICE pointer on the device that was current
+ *    when the cell was created, allocated and owned by the caller.  The
+ *    library never frees or retains it.
+ *  - Validation is synchronous; on any error nothing is launched and the
+ *    status says why (gw_last_error() gives detail, per thread).  Kernels are
+ *    enqueued on `stream` (a hipStream_t; NULL is the null stream) and the
+ *    call returns without synchronising.  Calls on different cells or
+ *    streams may run concurrently; a cell is read-only after creation.
+ */
+#ifndef GWR_H
+#define GWR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GW_OK = 0,
+  GW_ERR_ARG = -1,         /* null pointer, bad enum, non-symmetric C, aliasing ... */
+  GW_ERR_SHAPE = -2,       /* sizes inconsistent or out of the supported range     */
+  GW_ERR_NOMEM = -3,       /* device allocation failed during gw_cell_create       */
+  GW_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed           */
+  GW_ERR_UNSUPPORTED = -5  /* valid request this build does not implement          */
+} gw_status;
+
+/* Arithmetic of the P and Sigma contractions (Eqs. (5), (8)).
+ *   GW_FP64   : G, W, P are complex128; FP64 MFMA; Sigma complex128.
+ *   GW_FP32   : G, W, P are complex64; FP32 MFMA, FP32 accumulation;
+ *               Sigma is accumulated over atom-orbital sums in FP64 and stored complex128.
+ *   GW_BF16X3 : G, W, P are complex64; each FP32 operand split into bf16 hi + lo and
+ *               the products hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation;
+ *               Sigma as for GW_FP32. */
+typedef enum { GW_FP64 = 0, GW_FP32 = 1, GW_BF16X3 = 2 } gw_precision;
+
+/* Storage type of a transform operand.  Transforms always compute in FP64. */
+typedef enum { GW_C128 = 0, GW_C64 = 1 } gw_dtype;
+
+typedef struct gw_cell gw_cell;
+
+/* Create a cell description and upload its constants (product-basis
+ * coefficients in every layout the kernels use) to the current device.
+ *   species_of_atom[n_atoms] in [0, n_species);  n_orb[n_species], n_pb[n_species] >= 1;
+ *   C: host FP64, species after species, each [n_pb[s]][n_orb[s]][n_orb[s]] holding
+ *      <M_I | phi_a phi_b> (Eqs. (5), (8)); must be symmetric in (a, b) to 1e-12
+ *      relative, else GW_ERR_ARG (the kernels fold that symmetry);
+ *   mesh[3] >= 1 each; n_tau >= 2; beta > 0.
+ * Limits: n_orb <= 16, n_pb <= 128, N_R <= 64 (GW_ERR_SHAPE beyond).
+ * On success *out owns device memory until gw_cell_destroy. */
+gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom, int n_species,
+                         const int* n_orb, const int* n_pb, const double* C, const int* mesh,
+                         int n_tau, double beta);
+void gw_cell_destroy(gw_cell* cell);
+
+/* Totals of a cell (0 for a NULL cell). */
+int gw_cell_n_orb_total(const gw_cell* cell);
+int gw_cell_n_pb_total(const gw_cell* cell);
+int gw_cell_n_R(const gw_cell* cell);
+
+/* k -> R lattice sum (Sec. 2): out^R = N_k^-1 sum_k exp(+i k.R) in(k), per tau and
+ * per matrix element; basis 0 (N_orb) or 1 (N_pb); in and out may be the same
+ * pointer when in_type == out_type (in-place), otherwise they must not overlap. */
+gw_status gw_fourier_k2r(const gw_cell* cell, const void* in, gw_dtype in_type, void* out,
+                         gw_dtype out_type, int basis, void* stream);
+
+/* R -> k lattice sum: out(k) = sum_R exp(-i k.R) in^R.  Same rules as gw_fourier_k2r. */
+gw_status gw_fourier_r2k(const gw_cell* cell, const void* in, gw_dtype in_type, void* out,
+                         gw_dtype out_type, int basis, void* stream);
+
+/* Polarizability, Eq. (5) (MT-MT), for every (tau, R, A, B):
+ *   P^R_IJ(tau) = -g sum_{a,b in A; c,d in B} C^I_ab G^R_ac(tau) G^{-R}_db(beta - tau) C^J_cd
+ * GR: [n_tau][N_R][N_orb][N_orb], P: [n_tau][N_R][N_pb][N_pb], complex128 for GW_FP64,
+ * complex64 otherwise; g = spin_factor (the spin sum of Eq. (5)).  Uses the identity
+ * P^R_IJ(beta - tau) = P^{-R}_JI(tau) (symmetric C) to evaluate half the tau range. */
+gw_status gw_polarizability(const gw_cell* cell, const void* GR, void* P, double spin_factor,
+                            gw_precision prec, void* stream);
+
+/* Self-energy, Eq. (8) (MT-MT), with W taken at the same tau as G:
+ *   Sigma^R_ab(tau) = -sum_{a',I in A; b',J in B} C^I_aa' G^R_a'b'(tau) W^R_IJ(tau) C^J_bb'
+ * GR, WR: complex128 for GW_FP64, complex64 otherwise; Sigma always complex128,
+ * [n_tau][N_R][N_orb][N_orb]. */
+gw_status gw_self_energy(const gw_cell* cell, const void* GR, const void* WR, void* Sigma,
+                         gw_precision prec, void* stream);
+
+/* Imaginary time -> Matsubara frequency along the leading axis:
+ *   out[m][...] = sum_i T[m][i] in[i][...],  m < n_omega,
+ * with T a DEVICE complex128 matrix [n_omega][n_tau] (see gw_tau2omega_matrix).
+ * The trailing shape is [N_R][n][n] with n = N_orb (basis 0) or N_pb (basis 1).
+ * FP64 arithmetic.  in == out is allowed when in_type == out_type. */
+gw_status gw_tau2omega(const gw_cell* cell, const void* T, int n_omega, const void* in,
+                       gw_dtype in_type, void* out, gw_dtype out_type, int basis, void* stream);
+
+/* R -> k followed by tau -> Matsubara in one pass over HBM (product of the two
+ * operators above; same argument rules). */
+gw_status gw_drain(const gw_cell* cell, const void* T, int n_omega, const void* in,
+                   gw_dtype in_type, void* out, gw_dtype out_type, int basis, void* stream);
+
+/* Electron count for the chemical-potential update (Sec. 4):
+ *   n = -g sum_a Re G^{R=0}_aa(beta^-)   (the last tau point),
+ * written as one FP64 value to the DEVICE pointer n_dev.  GR in gr_type storage. */
+gw_status gw_density(const gw_cell* cell, const void* GR, gw_dtype gr_type, double spin_factor,
+                     double* n_dev, void* stream);
+
+/* Host helper: the FP64 matrix T[n_omega][n_tau] (complex, interleaved) that integrates
+ * the piecewise-linear interpolant of F(tau) against exp(i omega_m tau) over [0, beta]
+ * exactly (trapezoid rule at omega = 0).  tau: host, increasing; omega: host.
+ * T_host: host buffer of 2*n_omega*n_tau doubles. */
+gw_status gw_tau2omega_matrix(int n_tau, const double* tau, int n_omega, const double* omega,
+                              double* T_host);
+
+const char* gw_status_string(gw_status s);
+const char* gw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWR_H */

@@ -1,0 +1,230 @@
+"""Python binding of libgwr (space-time P / Sigma on MI355X).
+
+Argument marshalling only: every call checks the tensors (device, dtype,
+contiguity, element count against the cell), passes raw device pointers and
+the current HIP stream to the C ABI declared in include/gwr.h, and turns a
+non-zero status into GWError.  All arithmetic runs in the library's kernels.
+If libgwr.so is missing the import of this module fails: there is no other
+code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgwr.so")
+
+GW_OK, GW_ERR_ARG, GW_ERR_SHAPE, GW_ERR_NOMEM, GW_ERR_HIP, GW_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+GW_FP64, GW_FP32, GW_BF16X3 = 0, 1, 2
+GW_C128, GW_C64 = 0, 1
+PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "bf16x3": GW_BF16X3}
+
+# every function the header declares, with its ctypes signature
+_c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+_ip, _dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "gw_cell_create": (_c_int, [ctypes.POINTER(_vp), _c_int, _ip, _c_int, _ip, _ip, _dp, _ip, _c_int, _c_double]),
+    "gw_cell_destroy": (None, [_vp]),
+    "gw_cell_n_orb_total": (_c_int, [_vp]),
+    "gw_cell_n_pb_total": (_c_int, [_vp]),
+    "gw_cell_n_R": (_c_int, [_vp]),
+    "gw_fourier_k2r": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
+    "gw_fourier_r2k": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
+    "gw_polarizability": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
+    "gw_self_energy": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
+    "gw_tau2omega": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
+    "gw_drain": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
+    "gw_density": (_c_int, [_vp, _vp, _c_int, _c_double, _vp, _vp]),
+    "gw_tau2omega_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
+    "gw_status_string": (ctypes.c_char_p, [_c_int]),
+    "gw_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1911_05633_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class GWError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib.gw_status_string(status).decode()
+        detail = lib.gw_last_error().decode()
+        super().__init__(f"{where}: {msg} ({detail})")
+
+
+def _check(st, where):
+    if st != GW_OK:
+        raise GWError(st, where)
+
+
+def _torch():
+    import torch  # deferred: the CPU-only tests load the library without torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return GW_C128
+    if t.dtype == torch.complex64:
+        return GW_C64
+    raise TypeError(f"expected complex128 or complex64, got {t.dtype}")
+
+
+def _ptr(t, numel, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Cell:
+    """Owns a gw_cell handle (constants on the current device)."""
+
+    def __init__(self, species_of_atom, n_orb, n_pb, C, mesh, n_tau, beta):
+        species = np.ascontiguousarray(species_of_atom, dtype=np.int32)
+        n_orb = np.ascontiguousarray(n_orb, dtype=np.int32)
+        n_pb = np.ascontiguousarray(n_pb, dtype=np.int32)
+        Cflat = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.float64).ravel() for c in C]))
+        mesh = np.ascontiguousarray(mesh, dtype=np.int32)
+        h = ctypes.c_void_p()
+        st = lib.gw_cell_create(ctypes.byref(h), len(species), species.ctypes.data_as(_ip), len(n_orb),
+                                n_orb.ctypes.data_as(_ip), n_pb.ctypes.data_as(_ip), Cflat.ctypes.data_as(_dp),
+                                mesh.ctypes.data_as(_ip), int(n_tau), float(beta))
+        _check(st, "gw_cell_create")
+        self.handle = h
+        self.n_tau = int(n_tau)
+        self.beta = float(beta)
+        self.mesh = tuple(int(x) for x in mesh)
+        self.N_orb = lib.gw_cell_n_orb_total(h)
+        self.N_pb = lib.gw_cell_n_pb_total(h)
+        self.N_R = lib.gw_cell_n_R(h)
+
+    @classmethod
+    def from_spec(cls, spec, C):
+        return cls(spec.species, spec.n_orb, spec.n_pb, C, spec.mesh, spec.n_tau, spec.beta)
+
+    def n_basis(self, basis):
+        return self.N_orb if basis == 0 else self.N_pb
+
+    def elems(self, basis, lead=None):
+        n = self.n_basis(basis)
+        return (self.n_tau if lead is None else lead) * self.N_R * n * n
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gw_cell_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gw_fourier_k2r(cell, inp, out, basis=0):
+    n = cell.elems(basis)
+    _check(lib.gw_fourier_k2r(cell.handle, _ptr(inp, n, "in"), _dtype_code(inp), _ptr(out, n, "out"),
+                              _dtype_code(out), basis, _stream()), "gw_fourier_k2r")
+
+
+def gw_fourier_r2k(cell, inp, out, basis=0):
+    n = cell.elems(basis)
+    _check(lib.gw_fourier_r2k(cell.handle, _ptr(inp, n, "in"), _dtype_code(inp), _ptr(out, n, "out"),
+                              _dtype_code(out), basis, _stream()), "gw_fourier_r2k")
+
+
+def _prec(prec, t):
+    if prec is None:
+        return GW_FP64 if _dtype_code(t) == GW_C128 else GW_FP32
+    return PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+
+
+def gw_polarizability(cell, GR, P, spin_factor=2.0, prec=None):
+    p = _prec(prec, GR)
+    want = GW_C128 if p == GW_FP64 else GW_C64
+    if _dtype_code(GR) != want or _dtype_code(P) != want:
+        raise TypeError("GR and P must be complex128 for fp64 and complex64 otherwise")
+    _check(lib.gw_polarizability(cell.handle, _ptr(GR, cell.elems(0), "GR"), _ptr(P, cell.elems(1), "P"),
+                                 float(spin_factor), p, _stream()), "gw_polarizability")
+
+
+def gw_self_energy(cell, GR, WR, Sigma, prec=None):
+    p = _prec(prec, GR)
+    want = GW_C128 if p == GW_FP64 else GW_C64
+    if _dtype_code(GR) != want or _dtype_code(WR) != want:
+        raise TypeError("GR and WR must be complex128 for fp64 and complex64 otherwise")
+    if _dtype_code(Sigma) != GW_C128:
+        raise TypeError("Sigma is always complex128")
+    _check(lib.gw_self_energy(cell.handle, _ptr(GR, cell.elems(0), "GR"), _ptr(WR, cell.elems(1), "WR"),
+                              _ptr(Sigma, cell.elems(0), "Sigma"), p, _stream()), "gw_self_energy")
+
+
+def _T_ptr(cell, T):
+    torch = _torch()
+    if T.dtype != torch.complex128 or T.dim() != 2 or T.shape[1] != cell.n_tau:
+        raise ValueError("T must be a complex128 device matrix [n_omega][n_tau]")
+    return _ptr(T, T.numel(), "T"), int(T.shape[0])
+
+
+def gw_tau2omega(cell, T, inp, out, basis=0):
+    tp, n_omega = _T_ptr(cell, T)
+    _check(lib.gw_tau2omega(cell.handle, tp, n_omega, _ptr(inp, cell.elems(basis), "in"), _dtype_code(inp),
+                            _ptr(out, cell.elems(basis, n_omega) if out.data_ptr() != inp.data_ptr()
+                                 else out.numel(), "out"),
+                            _dtype_code(out), basis, _stream()), "gw_tau2omega")
+
+
+def gw_drain(cell, T, inp, out, basis=1):
+    tp, n_omega = _T_ptr(cell, T)
+    _check(lib.gw_drain(cell.handle, tp, n_omega, _ptr(inp, cell.elems(basis), "in"), _dtype_code(inp),
+                        _ptr(out, cell.elems(basis, n_omega) if out.data_ptr() != inp.data_ptr()
+                             else out.numel(), "out"),
+                        _dtype_code(out), basis, _stream()), "gw_drain")
+
+
+def gw_density(cell, GR, spin_factor, n_out):
+    torch = _torch()
+    if n_out.dtype != torch.float64 or n_out.numel() != 1:
+        raise ValueError("n_out must be a one-element float64 device tensor")
+    _check(lib.gw_density(cell.handle, _ptr(GR, cell.elems(0), "GR"), _dtype_code(GR), float(spin_factor),
+                          _ptr(n_out, 1, "n_out"), _stream()), "gw_density")
+
+
+def gw_tau2omega_matrix(tau, omega):
+    """Host FP64 matrix T[n_omega][n_tau] (numpy complex128)."""
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros((len(omega), len(tau)), dtype=np.complex128)
+    _check(lib.gw_tau2omega_matrix(len(tau), tau.ctypes.data_as(_dp), len(omega), omega.ctypes.data_as(_dp),
+                                   out.ctypes.data_as(_dp)), "gw_tau2omega_matrix")
+    return out
+
+
+def matsubara(n, beta, kind):
+    """First n Matsubara frequencies: bosonic 2 pi m / beta or fermionic (2m + 1) pi / beta."""
+    m = np.arange(n, dtype=np.float64)
+    return (2.0 * m if kind == "bosonic" else 2.0 * m + 1.0) * np.pi / beta

@@ -1,0 +1,84 @@
+// Internal declarations of libgwr (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gwr.h"
+
+namespace gwr {
+
+constexpr int kMaxOrb = 16;
+constexpr int kMaxPb = 128;
+constexpr int kMaxR = 64;
+constexpr int kMaxPairs = kMaxOrb * (kMaxOrb + 1) / 2;  // 136
+
+// Per-species device constants.
+struct SpeciesDev {
+  int n = 0, m = 0;     // orbitals, product functions
+  int np = 0;           // unordered orbital pairs n(n+1)/2
+  int np_pad = 0;       // np rounded up to a multiple of 8
+  int m_pad = 0;        // m rounded up to a multiple of 16
+  double* C = nullptr;          // [m][n][n] FP64 (plain layout)
+  float* C32 = nullptr;         // [m][n][n] FP32
+  double* Cpair = nullptr;      // [m_pad][np_pad] FP64, C^I_{ab} at pair p = {a <= b}, zero padded
+  float* Cpair32 = nullptr;     // same, FP32
+  std::vector<int> atoms;       // atoms of this species (host)
+  int* atoms_dev = nullptr;     // same on device
+};
+
+struct PairTables {
+  // unordered pair p -> (a, b), a <= b, row-major over a then b >= a, per orbital count n
+  unsigned char a[kMaxPairs];
+  unsigned char b[kMaxPairs];
+};
+
+}  // namespace gwr
+
+struct gw_cell {
+  int device = 0;
+  int n_atoms = 0, n_species = 0;
+  std::vector<int> species;            // per atom
+  std::vector<int> n_orb, n_pb;        // per species
+  std::vector<int> orb_off, pb_off;    // per atom, size n_atoms + 1
+  int N_orb = 0, N_pb = 0;
+  int mesh[3] = {1, 1, 1};
+  int N_R = 1;
+  int n_tau = 0;
+  double beta = 0;
+  std::vector<int> minusR;             // host
+  int* minusR_dev = nullptr;
+  int* orb_off_dev = nullptr;
+  int* pb_off_dev = nullptr;
+  int* species_dev = nullptr;
+  std::vector<gwr::SpeciesDev> sp;
+  std::vector<void*> owned;            // every device allocation, freed at destroy
+};
+
+namespace gwr {
+
+// thread-local error detail
+void set_error(const std::string& msg);
+gw_status fail(gw_status s, const std::string& msg);
+gw_status check_launch(const char* what);
+
+inline size_t csize(gw_dtype t) { return t == GW_C128 ? 16 : 8; }
+
+// launchers (defined in the kernel sources); all validation is done by the caller
+gw_status launch_fourier(const gw_cell* c, const void* in, gw_dtype it, void* out, gw_dtype ot,
+                         int n, int sign, hipStream_t s);
+gw_status launch_tau2omega(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it,
+                           void* out, gw_dtype ot, long long cols, hipStream_t s);
+gw_status launch_drain(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it,
+                       void* out, gw_dtype ot, int n, hipStream_t s);
+gw_status launch_polarizability(const gw_cell* c, const void* GR, void* P, double g, gw_precision p,
+                                hipStream_t s);
+gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, void* S,
+                             gw_precision p, hipStream_t s);
+gw_status launch_density(const gw_cell* c, const void* GR, gw_dtype t, double g, double* n_dev,
+                         hipStream_t s);
+
+}  // namespace gwr

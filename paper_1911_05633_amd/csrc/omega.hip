@@ -1,0 +1,269 @@
+// Imaginary time -> Matsubara frequency transform, alone and fused with R -> k.
+//
+//   out[m][q][e] = sum_tau T[m][tau] sum_R exp(-i q.R) in[tau][R][e]        (gw_drain)
+//   out[m][c]    = sum_tau T[m][tau] in[tau][c]                             (gw_tau2omega)
+//
+// The tau contraction is a real GEMM with the 2x2 block form of the complex
+// matrix T, [[Tr, -Ti], [Ti, Tr]] (2 n_omega x 2 n_tau), applied to columns of
+// interleaved (re, im) data; it runs on the FP64 MFMA (16x16x4).  A workgroup
+// owns up to 64 output columns (CB matrix elements times N_R lattice vectors):
+// it stages every tau and R of those elements in LDS with contiguous loads, does
+// the separable R -> k sum in registers, then each of its 4 wavefronts computes
+// one 16-column tile over all frequencies and writes it back.  Each column is
+// read and written exactly once, so in == out (in-place) is safe.
+#include "cplx.h"
+#include "internal.h"
+
+namespace gwr {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kDrainMaxTau = 96;
+constexpr int kDrainMaxOmega = 96;
+constexpr int kDrainCols = 64;
+
+template <int O, int L, int S>
+__device__ __forceinline__ void dft_pass_minus(double* re, double* im) {
+  if constexpr (L == 1) {
+    return;
+  } else {
+    double cw[L], sw[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) turn(-(double)m / (double)L, cw[m], sw[m]);
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        double xr[L], xi[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          xr[l] = re[(o * L + l) * S + i];
+          xi[l] = im[(o * L + l) * S + i];
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+          double ar = 0, ai = 0;
+#pragma unroll
+          for (int l = 0; l < L; ++l) {
+            const int m = (j * l) % L;
+            ar += cw[m] * xr[l] - sw[m] * xi[l];
+            ai += cw[m] * xi[l] + sw[m] * xr[l];
+          }
+          re[(o * L + j) * S + i] = ar;
+          im[(o * L + j) * S + i] = ai;
+        }
+      }
+    }
+  }
+}
+
+// grid: one block per CB-element chunk; 256 threads = 4 wavefronts, one 16-column tile each.
+template <int N1, int N2, int N3, class TI, class TO>
+__global__ __launch_bounds__(256) void drain_mfma(const double2* __restrict__ T, int n_omega, int n_tau,
+                                                  const TI* in, TO* out, long long n2, int CB) {
+  constexpr int NR = N1 * N2 * N3;
+  extern __shared__ double2 ysh[];  // [n_tau rounded up to even][kDrainCols]
+  auto y = reinterpret_cast<double2(*)[kDrainCols]>(ysh);
+  const int tid = threadIdx.x;
+  const long long e0 = (long long)blockIdx.x * CB;
+  const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);  // live elements in this chunk
+  const int ncol = NR * CB;
+
+  // phase 1: stage in[tau][R][e0 .. e0+cb) as y[tau][R*CB + c]
+  for (int idx = tid; idx < n_tau * ncol; idx += 256) {
+    const int t = idx / ncol, rc = idx - t * ncol, R = rc / CB, c = rc - R * CB;
+    double a = 0, b = 0;
+    if (c < cb) ldc(in + ((long long)t * NR + R) * n2 + e0 + c, a, b);
+    y[t][rc] = make_double2(a, b);
+  }
+  for (int idx = tid; idx < n_tau * (kDrainCols - ncol); idx += 256) {  // zero the padding columns
+    const int t = idx / (kDrainCols - ncol), rc = ncol + idx % (kDrainCols - ncol);
+    y[t][rc] = make_double2(0.0, 0.0);
+  }
+  if (n_tau & 1)
+    for (int rc = tid; rc < kDrainCols; rc += 256) y[n_tau][rc] = make_double2(0.0, 0.0);
+  __syncthreads();
+
+  // phase 2: R -> k for every (tau, c), separable passes in registers, back into LDS
+  if constexpr (NR > 1) {
+    for (int idx = tid; idx < n_tau * CB; idx += 256) {
+      const int t = idx / CB, c = idx - t * CB;
+      double re[NR], im[NR];
+#pragma unroll
+      for (int R = 0; R < NR; ++R) {
+        const double2 v = y[t][R * CB + c];
+        re[R] = v.x;
+        im[R] = v.y;
+      }
+      dft_pass_minus<N1 * N2, N3, 1>(re, im);
+      dft_pass_minus<N1, N2, N3>(re, im);
+      dft_pass_minus<1, N1, N2 * N3>(re, im);
+#pragma unroll
+      for (int q = 0; q < NR; ++q) y[t][q * CB + c] = make_double2(re[q], im[q]);
+    }
+    __syncthreads();
+  }
+
+  // phase 3: FP64 MFMA over tau.  Row r of an M tile (16 rows) is (m, part) with
+  // m = 8*mt + 4*(r/8) + r%4 and part = (r/4)%2, so the D fragment of a lane holds the
+  // (re, im) pairs of two frequencies; k = 4*ks + l/16 is (tau = 2*ks + k%4/2, part' = k%2).
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt_count = (2 * n_omega + 15) / 16;
+  const int ks_count = (n_tau + 1) / 2;
+  const int r = li;
+  const int m_off = 4 * (r >> 3) + (r & 3), part = (r >> 2) & 1;
+  const int tau_off = lk >> 1, partp = lk & 1;
+  const double sgn = (part == 0 && partp == 1) ? -1.0 : 1.0;
+  const bool use_im = part != partp;
+  const int col = 16 * w + li;
+  for (int mt0 = 0; mt0 < mt_count; mt0 += 6) {
+    d4 acc[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[i] = d4{0, 0, 0, 0};
+    for (int ks = 0; ks < ks_count; ++ks) {
+      const int tau = 2 * ks + tau_off;
+      const double2 yv = y[tau][col];
+      const double b = partp ? yv.y : yv.x;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const int m = 8 * (mt0 + i) + m_off;
+        double a = 0.0;
+        if (m < n_omega && tau < n_tau) {
+          const double2 tv = T[(long long)m * n_tau + tau];
+          a = sgn * (use_im ? tv.y : tv.x);
+        }
+        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+      }
+    }
+    // phase 4: lane holds rows lk + 4j: (re, im) of m = 8*mt + lk and of m = 8*mt + 4 + lk
+    const int q = col / CB, c = col - q * CB;
+    if (col < ncol && c < cb) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const int mA = 8 * (mt0 + i) + lk, mB = mA + 4;
+        if (mt0 + i < mt_count) {
+          if (mA < n_omega) stc(out + ((long long)mA * NR + q) * n2 + e0 + c, acc[i][0], acc[i][1]);
+          if (mB < n_omega) stc(out + ((long long)mB * NR + q) * n2 + e0 + c, acc[i][2], acc[i][3]);
+        }
+      }
+    }
+  }
+}
+
+// Plain FP64 VALU transform for sizes outside the MFMA kernel's range (tau <= 256).
+template <class TI, class TO>
+__global__ __launch_bounds__(256) void tau2omega_valu(const double2* __restrict__ T, int n_omega, int n_tau,
+                                                      const TI* in, TO* out, long long cols, int CB) {
+  extern __shared__ double2 xs[];  // [n_tau][CB]
+  const long long c0 = (long long)blockIdx.x * CB;
+  for (int idx = threadIdx.x; idx < n_tau * CB; idx += 256) {
+    const int t = idx / CB, c = idx - t * CB;
+    double a = 0, b = 0;
+    if (c0 + c < cols) ldc(in + (long long)t * cols + c0 + c, a, b);
+    xs[idx] = make_double2(a, b);
+  }
+  __syncthreads();
+  const int c = threadIdx.x % CB, g = threadIdx.x / CB, G = 256 / CB;
+  if (c0 + c >= cols) return;
+  for (int m = g; m < n_omega; m += G) {
+    double ar = 0, ai = 0;
+    for (int t = 0; t < n_tau; ++t) {
+      const double2 tv = T[(long long)m * n_tau + t];
+      const double2 v = xs[t * CB + c];
+      ar += tv.x * v.x - tv.y * v.y;
+      ai += tv.x * v.y + tv.y * v.x;
+    }
+    stc(out + (long long)m * cols + c0 + c, ar, ai);
+  }
+}
+
+template <int N1, int N2, int N3, class TI, class TO>
+void run_drain(const double2* T, int n_omega, int n_tau, const TI* in, TO* out, long long n2, hipStream_t s) {
+  constexpr int NR = N1 * N2 * N3;
+  const int CB = kDrainCols / NR;
+  const unsigned blocks = (unsigned)((n2 + CB - 1) / CB);
+  const size_t lds = (size_t)((n_tau + 1) / 2 * 2) * kDrainCols * sizeof(double2);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)drain_mfma<N1, N2, N3, TI, TO>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((drain_mfma<N1, N2, N3, TI, TO>), dim3(blocks), dim3(256), lds, s, T, n_omega, n_tau, in,
+                     out, n2, CB);
+}
+
+template <class TI, class TO>
+void run_valu(const double2* T, int n_omega, int n_tau, const TI* in, TO* out, long long cols, hipStream_t s) {
+  const int CB = n_tau <= 64 ? 64 : (n_tau <= 128 ? 32 : 16);
+  const unsigned blocks = (unsigned)((cols + CB - 1) / CB);
+  hipLaunchKernelGGL((tau2omega_valu<TI, TO>), dim3(blocks), dim3(256), (size_t)n_tau * CB * sizeof(double2), s,
+                     T, n_omega, n_tau, in, out, cols, CB);
+}
+
+bool mfma_ok(int n_tau, int n_omega) { return n_tau <= kDrainMaxTau && n_omega <= kDrainMaxOmega; }
+
+// dispatch on the mesh; returns false if the mesh has no fused kernel
+template <class TI, class TO>
+bool drain_dispatch(const gw_cell* c, const double2* T, int n_omega, const TI* in, TO* out, long long n2,
+                    hipStream_t s) {
+  const int a = c->mesh[0], b = c->mesh[1], d = c->mesh[2];
+#define GWR_DRAIN(x, y, z)                                                \
+  if (a == x && b == y && d == z) {                                       \
+    run_drain<x, y, z>(T, n_omega, c->n_tau, in, out, n2, s);             \
+    return true;                                                          \
+  }
+  GWR_DRAIN(1, 1, 1)
+  GWR_DRAIN(2, 2, 2)
+  GWR_DRAIN(2, 2, 1)
+  GWR_DRAIN(3, 2, 1)
+  GWR_DRAIN(4, 4, 4)
+  GWR_DRAIN(4, 4, 2)
+  GWR_DRAIN(2, 1, 1)
+#undef GWR_DRAIN
+  return false;
+}
+
+template <class TI, class TO>
+gw_status tau2omega_typed(const gw_cell* c, const double2* T, int n_omega, const TI* in, TO* out,
+                          long long cols, hipStream_t s) {
+  if (mfma_ok(c->n_tau, n_omega))
+    run_drain<1, 1, 1>(T, n_omega, c->n_tau, in, out, cols, s);
+  else
+    run_valu(T, n_omega, c->n_tau, in, out, cols, s);
+  return check_launch("tau2omega");
+}
+
+template <class TI, class TO>
+gw_status drain_typed(const gw_cell* c, const double2* T, int n_omega, const TI* in, TO* out, int n,
+                      gw_dtype ot, hipStream_t s) {
+  const long long n2 = (long long)n * n;
+  if (mfma_ok(c->n_tau, n_omega) && drain_dispatch(c, T, n_omega, in, out, n2, s)) return check_launch("drain");
+  // two passes through `out`: needs room for n_tau rows there
+  if ((const void*)in != (const void*)out && n_omega < c->n_tau)
+    return fail(GW_ERR_UNSUPPORTED, "this mesh / grid needs n_omega >= n_tau or an in-place drain");
+  gw_status st = launch_fourier(c, in, sizeof(TI) == 16 ? GW_C128 : GW_C64, out, ot, n, -1, s);
+  if (st != GW_OK) return st;
+  return tau2omega_typed(c, T, n_omega, out, out, (long long)c->N_R * n2, s);
+}
+
+}  // namespace
+
+gw_status launch_tau2omega(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it, void* out,
+                           gw_dtype ot, long long cols, hipStream_t s) {
+  const double2* Td = (const double2*)T;
+  if (it == GW_C128 && ot == GW_C128) return tau2omega_typed(c, Td, n_omega, (const double2*)in, (double2*)out, cols, s);
+  if (it == GW_C128 && ot == GW_C64) return tau2omega_typed(c, Td, n_omega, (const double2*)in, (float2*)out, cols, s);
+  if (it == GW_C64 && ot == GW_C128) return tau2omega_typed(c, Td, n_omega, (const float2*)in, (double2*)out, cols, s);
+  return tau2omega_typed(c, Td, n_omega, (const float2*)in, (float2*)out, cols, s);
+}
+
+gw_status launch_drain(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it, void* out,
+                       gw_dtype ot, int n, hipStream_t s) {
+  const double2* Td = (const double2*)T;
+  if (it == GW_C128 && ot == GW_C128) return drain_typed(c, Td, n_omega, (const double2*)in, (double2*)out, n, ot, s);
+  if (it == GW_C128 && ot == GW_C64) return drain_typed(c, Td, n_omega, (const double2*)in, (float2*)out, n, ot, s);
+  if (it == GW_C64 && ot == GW_C128) return drain_typed(c, Td, n_omega, (const float2*)in, (double2*)out, n, ot, s);
+  return drain_typed(c, Td, n_omega, (const float2*)in, (float2*)out, n, ot, s);
+}
+
+}  // namespace gwr

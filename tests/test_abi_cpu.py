@@ -1,0 +1,82 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+symbol, validates arguments before touching a device, and its host-side
+Matsubara matrix agrees with the oracle's (independent) construction."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "gwr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gw_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1911_05633_amd as g
+    names = declared_symbols()
+    assert len(names) >= 14
+    raw = ctypes.CDLL(g.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(names) == set(g.SIGNATURES)
+
+
+def test_validation_without_device():
+    import paper_1911_05633_amd as g
+    lib = g.lib
+    assert lib.gw_polarizability(None, None, None, 2.0, 0, None) == g.GW_ERR_ARG
+    assert lib.gw_self_energy(None, None, None, None, 0, None) == g.GW_ERR_ARG
+    assert lib.gw_fourier_k2r(None, None, 0, None, 0, 0, None) == g.GW_ERR_ARG
+    assert lib.gw_drain(None, None, 48, None, 0, None, 0, 1, None) == g.GW_ERR_ARG
+    assert lib.gw_density(None, None, 0, 2.0, None, None) == g.GW_ERR_ARG
+    h = ctypes.c_void_p()
+    sp = np.zeros(2, dtype=np.int32)
+    no = np.array([4], dtype=np.int32)
+    npb = np.array([16], dtype=np.int32)
+    mesh = np.array([2, 2, 2], dtype=np.int32)
+    C = np.zeros(16 * 16, dtype=np.float64)
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    # n_tau out of range, mesh entry 0, orbital count above the limit, bad species index
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(mesh), 1, 10.0) == g.GW_ERR_SHAPE
+    bad_mesh = np.array([2, 0, 2], dtype=np.int32)
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(bad_mesh), 8, 10.0) == g.GW_ERR_SHAPE
+    big = np.array([17], dtype=np.int32)
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(big), ip(npb), dp(C), ip(mesh), 8, 10.0) == g.GW_ERR_SHAPE
+    sp_bad = np.array([0, 3], dtype=np.int32)
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp_bad), 1, ip(no), ip(npb), dp(C), ip(mesh), 8, 10.0) == g.GW_ERR_ARG
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(mesh), 8, -1.0) == g.GW_ERR_ARG
+    assert b"beta" in lib.gw_last_error()
+
+
+@pytest.mark.parametrize("kind", ["bosonic", "fermionic"])
+def test_host_matsubara_matrix_matches_oracle(kind):
+    import paper_1911_05633_amd as g
+    beta, n = 200.0, 48
+    tau = beta * np.arange(n) / (n - 1)
+    w = g.matsubara(n, beta, kind)
+    ref_w = oracle.bosonic_frequencies(n, beta) if kind == "bosonic" else oracle.fermionic_frequencies(n, beta)
+    assert np.array_equal(w, ref_w)
+    T = g.gw_tau2omega_matrix(tau, w)
+    To = oracle.filon_matrix(tau, ref_w)
+    assert np.max(np.abs(T - To)) / np.max(np.abs(To)) < 1e-12
+
+
+def test_host_matsubara_matrix_nonuniform_grid():
+    import paper_1911_05633_amd as g
+    beta, n = 50.0, 33
+    tau = 0.5 * beta * (1 - np.cos(np.pi * np.arange(n) / (n - 1)))
+    w = oracle.fermionic_frequencies(20, beta)
+    T = g.gw_tau2omega_matrix(tau, w)
+    To = oracle.filon_matrix(tau, w)
+    assert np.max(np.abs(T - To)) / np.max(np.abs(To)) < 1e-11
+    with pytest.raises(g.GWError):
+        g.gw_tau2omega_matrix(tau[::-1].copy(), w)

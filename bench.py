@@ -1,0 +1,218 @@
+"""Benchmark of one space-time P + Sigma step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--prec fp64|fp32|bf16x3]
+
+A step is the whole path on one synthetic cell with inputs resident in HBM:
+    G(k,tau) -k2r-> G(R,tau) -> P (Eq. 5) and Sigma (Eq. 8, with W(R,tau))
+    -> drain (R->k, tau->Matsubara) of P and of Sigma -> electron count.
+The metric is the algorithmic P + Sigma GFLOP/s of the whole step.  One JSON
+line is printed with a roofline entry for the dominant kernel (timed with
+events on the launch stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+HBM_PEAK = 8.0e12
+
+
+def pair_flops(spec):
+    """Algorithmic P and Sigma flops per (tau, R) slice: sum over atom pairs of the cheapest
+    contraction order (complex x real MAC = 4 flop, complex x complex MAC = 8 flop)."""
+    n = spec.atom_norb
+    m = spec.atom_npb
+    fp = fs = 0.0
+    for A in range(spec.n_atoms):
+        nA, mA = float(n[A]), float(m[A])
+        nB, mB = n.astype(float), m.astype(float)
+        p1 = 4 * mA * nA * nA * nB + 8 * mA * nA * nB * nB + 4 * mA * mB * nB * nB
+        p2 = 4 * mB * nB * nB * nA + 8 * mB * nB * nA * nA + 4 * mA * mB * nA * nA
+        s1 = 4 * mA * mB * nB * nB + 4 * mA * nA * nA * nB + 8 * mA * nA * nB * nB
+        s2 = 4 * mA * mB * nA * nA + 4 * mB * nB * nB * nA + 8 * mB * nB * nA * nA
+        fp += np.minimum(p1, p2).sum()
+        fs += np.minimum(s1, s2).sum()
+    return fp, fs
+
+
+def build_inputs(spec, prec, torch, log):
+    import synthcell as sc
+    import paper_1911_05633_amd as g
+
+    t0 = time.time()
+    hop = sc.hoppings(spec)
+    b = sc.bands(spec, hop)
+    C = sc.coefficients(spec)
+    Gk_h = sc.green_ktau(spec, b)
+    A = sc.w_amplitude(spec)
+    sR, et = sc.w_factors(spec)
+    log(f"inputs built on host in {time.time() - t0:.1f}s")
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    Gk = torch.from_numpy(Gk_h).cuda()
+    GR = torch.empty(Gk.shape, dtype=cdt, device="cuda")
+    Ad = torch.from_numpy(A).cuda().to(torch.float64)
+    W = torch.empty((spec.n_tau, spec.N_R, spec.N_pb, spec.N_pb), dtype=cdt, device="cuda")
+    for t in range(spec.n_tau):
+        for R in range(spec.N_R):
+            W[t, R].copy_(Ad * float(sR[R] * et[t]))
+    del Ad
+    P = torch.empty((spec.n_tau, spec.N_R, spec.N_pb, spec.N_pb), dtype=cdt, device="cuda")
+    S = torch.empty((spec.n_tau, spec.N_R, spec.N_orb, spec.N_orb), dtype=torch.complex128, device="cuda")
+    tau = sc.tau_grid(spec)
+    TP = torch.from_numpy(g.gw_tau2omega_matrix(tau, g.matsubara(spec.n_tau, spec.beta, "bosonic"))).cuda()
+    TS = torch.from_numpy(g.gw_tau2omega_matrix(tau, g.matsubara(spec.n_tau, spec.beta, "fermionic"))).cuda()
+    nd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    return dict(C=C, Gk=Gk, GR=GR, W=W, P=P, S=S, TP=TP, TS=TS, n=nd, Gk_h=Gk_h, A=A, sR=sR, et=et)
+
+
+KERNELS = ["k2r", "P", "Sigma", "drain_P", "drain_Sigma", "density"]
+
+
+def run_step(g, cell, d, spec, prec, ev=None):
+    """One pass of the whole path; ev: list of (start, end) events per kernel, or None."""
+    calls = [
+        lambda: g.gw_fourier_k2r(cell, d["Gk"], d["GR"], basis=0),
+        lambda: g.gw_polarizability(cell, d["GR"], d["P"], spec.spin, prec=prec),
+        lambda: g.gw_self_energy(cell, d["GR"], d["W"], d["S"], prec=prec),
+        lambda: g.gw_drain(cell, d["TP"], d["P"], d["P"], basis=1),
+        lambda: g.gw_drain(cell, d["TS"], d["S"], d["S"], basis=0),
+        lambda: g.gw_density(cell, d["GR"], spec.spin, d["n"]),
+    ]
+    for i, f in enumerate(calls):
+        if ev is not None:
+            ev[i][0].record()
+        f()
+        if ev is not None:
+            ev[i][1].record()
+
+
+def kernel_roofs(spec, prec, fp, fs):
+    """Per kernel: (bound, algorithmic work per launch, peak, unit)."""
+    es = 16 if prec == "fp64" else 8
+    No, Np, NR, nt = spec.N_orb, spec.N_pb, spec.N_R, spec.n_tau
+    peak_mfma = PEAK["fp64"] if prec == "fp64" else (PEAK["fp32"] if prec == "fp32" else PEAK["bf16"])
+    roofs = {}
+    roofs["k2r"] = ("hbm", nt * NR * No * No * (16 + es), HBM_PEAK)
+    roofs["P"] = ("mfma", fp * nt * NR, peak_mfma)
+    roofs["Sigma"] = ("mfma", fs * nt * NR, peak_mfma)
+    # drain: FP64 MFMA tau contraction (8 n_omega n_tau flop per column) vs in+out bytes
+    for name, n, e in (("drain_P", Np, es), ("drain_Sigma", No, 16)):
+        flops = 8.0 * nt * nt * NR * n * n
+        byts = 2.0 * nt * NR * n * n * e
+        roofs[name] = ("mfma", flops, PEAK["fp64"]) if flops / PEAK["fp64"] > byts / HBM_PEAK else ("hbm", byts, HBM_PEAK)
+    roofs["density"] = ("hbm", No * 16, HBM_PEAK)
+    return roofs
+
+
+def cpu_baseline(spec, d, fp, fs, log):
+    """The FP64 oracle on a bounded sample: P^q(tau) for one (tau, q) and Sigma^k(tau) for one
+    (tau, k) of the same cell; scaled to the metric as (fraction of the step's work) / time."""
+    import oracle
+    import synthcell as sc
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    t = spec.n_tau // 3
+    t0 = time.perf_counter()
+    oracle.polarizability_q(d["Gk_h"], spec, d["C"], spec.spin, taus=[t], qs=[1])
+    tp = time.perf_counter() - t0
+    WR = {t: (d["et"][t] * d["sR"][:, None, None] * d["A"][None]).astype(np.complex128)}
+    t0 = time.perf_counter()
+    oracle.self_energy_k(d["Gk_h"], WR, spec, d["C"], taus=[t], ks=[1])
+    ts = time.perf_counter() - t0
+    frac = 1.0 / (spec.n_tau * spec.N_R)  # one (tau, q) slice of the whole P (and of Sigma)
+    work = frac * (fp + fs) * spec.n_tau * spec.N_R
+    log(f"cpu oracle sample: P {tp:.1f}s, Sigma {ts:.1f}s")
+    return {"value": work / (tp + ts) / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"k-space FP64 oracle: P^q(tau) for 1 tau x 1 q and Sigma^k(tau) for 1 tau x 1 k of "
+                      f"the {spec.n_atoms}-atom cell (each a 1/{spec.n_tau * spec.N_R} share of the step's "
+                      f"P or Sigma output); {tp + ts:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    import torch
+    import synthcell as sc
+    import paper_1911_05633_amd as g
+
+    spec = sc.config(args.config)
+    log(f"config {args.config}: {spec.name}, {spec.n_atoms} atoms, N_orb {spec.N_orb}, N_pb {spec.N_pb}, "
+        f"N_R {spec.N_R}, n_tau {spec.n_tau}, prec {args.prec}")
+    d = build_inputs(spec, args.prec, torch, log)
+    cell = g.Cell.from_spec(spec, d["C"])
+    fp, fs = pair_flops(spec)
+    for _ in range(args.warmup):
+        run_step(g, cell, d, spec, args.prec)
+    torch.cuda.synchronize()
+    log("warmup done")
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in KERNELS]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        run_step(g, cell, d, spec, args.prec, ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = {k: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]))
+           for i, k in enumerate(KERNELS)}
+    log("per-kernel ms: " + ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
+    ms = wall / args.steps * 1e3
+    total_flops = (fp + fs) * spec.n_tau * spec.N_R
+    roofs = kernel_roofs(spec, args.prec, fp, fs)
+    dom = max(per, key=per.get)
+    bound, work, peak = roofs[dom]
+    achieved = work / (per[dom] * 1e-3)
+    unit = "GB/s" if bound == "hbm" else "TFLOP/s"
+    scale = 1e9 if bound == "hbm" else 1e12
+    n_val = float(d["n"].cpu()[0])
+    out = {
+        "metric": "P+Sigma GFLOP/s per scGW step (72-atom Si-like cell); frac of MFMA peak in roofline",
+        "value": total_flops / (ms * 1e-3) / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name}: {spec.n_atoms} atoms, n_orb {spec.n_orb}, n_pb {spec.n_pb}, "
+                               f"mesh {'x'.join(map(str, spec.mesh))}, n_tau {spec.n_tau}, beta {spec.beta}",
+                   "precision": args.prec, "per_kernel_ms": per, "electron_count": n_val},
+        "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / scale, "peak": peak / scale,
+                     "unit": unit, "frac": achieved / peak, "traffic": None},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, d, fp, fs, log)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -129,7 +129,7 @@ gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom,
     d.n = n;
     d.m = m;
     d.np = n * (n + 1) / 2;
-    d.np_pad = round_up(d.np, 8);
+    d.np_pad = round_up(d.np, 16);
     d.m_pad = round_up(m, 16);
     const double* Cs = C + off;
     off += (size_t)m * n * n;

@@ -177,52 +177,37 @@ __global__ __launch_bounds__(256) void s_generic(const CT* __restrict__ GR, cons
 
 }  // namespace
 
-// Launch the generic kernels over all species pairs.
-template <class CT, class RT>
-static void p_generic_all(const gw_cell* c, const CT* GR, CT* P, double g, bool fp32, hipStream_t s) {
-  for (int sa = 0; sa < c->n_species; ++sa)
-    for (int sb = 0; sb < c->n_species; ++sb) {
-      const SpeciesDev &A = c->sp[sa], &B = c->sp[sb];
-      if (A.atoms.empty() || B.atoms.empty()) continue;
-      const long long blocks = (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
-      const RT* CA = fp32 ? (const RT*)A.C32 : (const RT*)A.C;
-      const RT* CBp = fp32 ? (const RT*)B.C32 : (const RT*)B.C;
-      hipLaunchKernelGGL((p_generic<CT, RT>), dim3((unsigned)blocks), dim3(256), 0, s, GR, P, CA, CBp, A.n, A.m,
-                         B.n, B.m, A.atoms_dev, (int)A.atoms.size(), B.atoms_dev, (int)B.atoms.size(),
-                         c->orb_off_dev, c->pb_off_dev, c->minusR_dev, c->N_R, c->n_tau, c->N_orb, c->N_pb, g);
-    }
-}
-
-template <class CT, class RT>
-static void s_generic_all(const gw_cell* c, const CT* GR, const CT* WR, double2* S, bool fp32, hipStream_t s) {
-  for (int sa = 0; sa < c->n_species; ++sa)
-    for (int sb = 0; sb < c->n_species; ++sb) {
-      const SpeciesDev &A = c->sp[sa], &B = c->sp[sb];
-      if (A.atoms.empty() || B.atoms.empty()) continue;
-      const long long blocks = (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
-      const RT* CA = fp32 ? (const RT*)A.C32 : (const RT*)A.C;
-      const RT* CBp = fp32 ? (const RT*)B.C32 : (const RT*)B.C;
-      hipLaunchKernelGGL((s_generic<CT, RT>), dim3((unsigned)blocks), dim3(256), 0, s, GR, WR, S, CA, CBp, A.n,
-                         A.m, B.n, B.m, A.atoms_dev, (int)A.atoms.size(), B.atoms_dev, (int)B.atoms.size(),
-                         c->orb_off_dev, c->pb_off_dev, c->N_R, c->N_orb, c->N_pb);
-    }
-}
-
-gw_status launch_p_generic(const gw_cell* c, const void* GR, void* P, double g, gw_precision p, hipStream_t s) {
+// Launch the generic kernels for one species pair.
+void launch_p_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
+                           double g, gw_precision p, hipStream_t s) {
+  const long long blocks = (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
+  if (blocks == 0) return;
   if (p == GW_FP64)
-    p_generic_all<double2, double>(c, (const double2*)GR, (double2*)P, g, false, s);
+    hipLaunchKernelGGL((p_generic<double2, double>), dim3((unsigned)blocks), dim3(256), 0, s, (const double2*)GR,
+                       (double2*)P, A.C, B.C, A.n, A.m, B.n, B.m, A.atoms_dev, (int)A.atoms.size(), B.atoms_dev,
+                       (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev, c->minusR_dev, c->N_R, c->n_tau,
+                       c->N_orb, c->N_pb, g);
   else
-    p_generic_all<float2, float>(c, (const float2*)GR, (float2*)P, g, true, s);
-  return check_launch("polarizability (generic)");
+    hipLaunchKernelGGL((p_generic<float2, float>), dim3((unsigned)blocks), dim3(256), 0, s, (const float2*)GR,
+                       (float2*)P, A.C32, B.C32, A.n, A.m, B.n, B.m, A.atoms_dev, (int)A.atoms.size(), B.atoms_dev,
+                       (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev, c->minusR_dev, c->N_R, c->n_tau,
+                       c->N_orb, c->N_pb, g);
 }
 
-gw_status launch_s_generic(const gw_cell* c, const void* GR, const void* WR, void* S, gw_precision p,
-                           hipStream_t s) {
+void launch_s_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
+                           const void* WR, void* S, gw_precision p, hipStream_t s) {
+  const long long blocks = (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
+  if (blocks == 0) return;
   if (p == GW_FP64)
-    s_generic_all<double2, double>(c, (const double2*)GR, (const double2*)WR, (double2*)S, false, s);
+    hipLaunchKernelGGL((s_generic<double2, double>), dim3((unsigned)blocks), dim3(256), 0, s, (const double2*)GR,
+                       (const double2*)WR, (double2*)S, A.C, B.C, A.n, A.m, B.n, B.m, A.atoms_dev,
+                       (int)A.atoms.size(), B.atoms_dev, (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev,
+                       c->N_R, c->N_orb, c->N_pb);
   else
-    s_generic_all<float2, float>(c, (const float2*)GR, (const float2*)WR, (double2*)S, true, s);
-  return check_launch("self-energy (generic)");
+    hipLaunchKernelGGL((s_generic<float2, float>), dim3((unsigned)blocks), dim3(256), 0, s, (const float2*)GR,
+                       (const float2*)WR, (double2*)S, A.C32, B.C32, A.n, A.m, B.n, B.m, A.atoms_dev,
+                       (int)A.atoms.size(), B.atoms_dev, (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev,
+                       c->N_R, c->N_orb, c->N_pb);
 }
 
 }  // namespace gwr

@@ -1,0 +1,398 @@
+// Eqs. (5) and (8) on the matrix cores (FP64 16x16x4 and FP32 16x16x4 MFMA).
+//
+// Both contractions are rewritten over UNORDERED orbital pairs, using that every
+// product-basis vertex C^I_ab is symmetric in (a, b): with p = {a, b} (45 pairs
+// for 9 orbitals) and C~^I_p = C^I_ab,
+//
+//   P_IJ     = -g sum_{p, p'} C~^I_p Q_{p p'} C~^J_p'
+//              Q_{{a,b},{c,d}} = sum over the distinct orderings (a1,b1) of {a,b}
+//                                and (c1,d1) of {c,d} of X_{a1 c1} Y_{d1 b1},
+//              X = G^R(tau)[A, B],  Y = G^{-R}(beta - tau)[B, A];
+//   Sigma_ab = -sum_{a', b'} X_{a'b'} K_{{a,a'},{b,b'}},
+//              K_{p, p'} = sum_I C~^I_p Z^I_p',  Z^I_p' = sum_J W_IJ C~^J_p',
+//              X = G^R(tau)[A, B],  W = W^R(tau)[A, B].
+//
+// Each becomes two chained real GEMMs with K = 48 (P: H = C~_A Q, then H C~_B^T;
+// Sigma: Z = W C~_B^T, then C~_A^T Z).  The D fragment of the first MFMA is
+// used in place as the B operand of the second: register j of an FP64
+// 16x16x4 D fragment holds rows g + 4j (g = lane / 16), exactly the k = g rows of
+// a 4-deep K step, so the first product's M rows are permuted such that the four
+// rows of a register share one (re | im) part and four consecutive pair indices.
+//
+// P additionally uses P^R_IJ(beta - tau) = P^{-R}_JI(tau) (symmetric C): only
+// tau_i with i <= n_tau - 1 - i is evaluated and every block is written twice.
+// Workgroups are persistent over (tau, R, A, B) blocks of one species pair and keep
+// the C~ operands they reuse in registers.
+#include "cplx.h"
+#include "internal.h"
+
+namespace gwr {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <class RT>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef d4 acc;
+  typedef double2 cplx;
+  static __device__ __forceinline__ d4 op(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // D fragment: register j of lane group g (= lane / 16) holds row g + 4 j
+  static __device__ __forceinline__ int drow(int g, int j) { return g + 4 * j; }
+  static __device__ __forceinline__ void split(int r, int& g, int& j) {
+    g = r & 3;
+    j = r >> 2;
+  }
+};
+template <>
+struct Mma<float> {
+  typedef f4 acc;
+  typedef float2 cplx;
+  static __device__ __forceinline__ f4 op(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // D fragment: register j of lane group g holds row 4 g + j
+  static __device__ __forceinline__ int drow(int g, int j) { return 4 * g + j; }
+  static __device__ __forceinline__ void split(int r, int& g, int& j) {
+    g = r >> 2;
+    j = r & 3;
+  }
+};
+
+constexpr int kPL = 48;       // padded pair count handled here (n <= 9)
+constexpr int kKA = kPL / 4;  // K steps over pairs
+constexpr int kTB = kPL / 8;  // 16-row tiles of (pair, part)
+constexpr int kMP = 64;       // padded product functions handled here (m <= 64)
+constexpr int kJT = kMP / 16;
+constexpr int kKJ = kMP / 4;
+
+template <class RT>
+__device__ __forceinline__ typename Mma<RT>::cplx mk(double re, double im) {
+  typename Mma<RT>::cplx v;
+  v.x = (RT)re;
+  v.y = (RT)im;
+  return v;
+}
+
+__device__ __forceinline__ void pair_of(int p, int n, unsigned char& a, unsigned char& b) {
+  int x = 0;
+  while (p >= n - x) {
+    p -= n - x;
+    ++x;
+  }
+  a = (unsigned char)x;
+  b = (unsigned char)(x + p);
+}
+
+__device__ __forceinline__ int pair_index(int a, int b, int n) {
+  if (a > b) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  return a * n - a * (a - 1) / 2 + (b - a);
+}
+
+struct PairArgs {
+  int nA, nB, mA, mB, npA, npB, nppA, nppB, mpA, mpB;
+  const int* atomsA;
+  int cntA;
+  const int* atomsB;
+  int cntB;
+  const int* orb_off;
+  const int* pb_off;
+  const int* minusR;
+  int NR, n_tau, n_half, No, Np;
+  long long nblocks;
+};
+
+// ---------------------------------------------------------------------------
+// polarizability
+// ---------------------------------------------------------------------------
+template <class RT, class CT>
+__global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* __restrict__ P,
+                                                 const RT* __restrict__ CpA, const RT* __restrict__ CpB,
+                                                 const PairArgs q, double g) {
+  using M = Mma<RT>;
+  typedef typename M::cplx CR;
+  __shared__ CR Xs[kMaxOrb * kMaxOrb], Ys[kMaxOrb * kMaxOrb];
+  __shared__ CR Qs[kPL * kPL];
+  __shared__ unsigned char ta[kPL], tb[kPL], tc[kPL], td[kPL];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  if (tid < q.npA) pair_of(tid, q.nA, ta[tid], tb[tid]);
+  if (tid < q.npB) pair_of(tid, q.nB, tc[tid], td[tid]);
+  const int nKA = q.nppA / 4, nTB = q.nppB / 8, nJT = (q.mB + 15) / 16, nIT = q.mpA / 16;
+
+  // second product's A operand, C~_B[J][p'], J = 16 Jt + li, p' = 8 t + 4 h + lk
+  RT a2[kJT][kTB][2];
+#pragma unroll
+  for (int Jt = 0; Jt < kJT; ++Jt)
+#pragma unroll
+    for (int t = 0; t < kTB; ++t)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        a2[Jt][t][h] = (Jt < nJT && t < nTB) ? CpB[(16 * Jt + li) * q.nppB + 8 * t + 4 * h + lk] : RT(0);
+  int rg, rj;
+  M::split(li, rg, rj);
+  const int row_pp = 4 * (rj >> 1) + rg, row_part = rj & 1;
+  const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+  const RT* Qd = reinterpret_cast<const RT*>(Qs);
+  __syncthreads();
+
+  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
+    long long b = blk;
+    const int iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    const int iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    const int R = (int)(b % q.NR);
+    const int t = (int)(b / q.NR);
+    const int A = q.atomsA[iA], B = q.atomsB[iB];
+    const int tm = q.n_tau - 1 - t, mR = q.minusR[R];
+    const int oA = q.orb_off[A], oB = q.orb_off[B], pA = q.pb_off[A], pB = q.pb_off[B];
+    const CT* Gt = GR + ((long long)t * q.NR + R) * sl;
+    const CT* Gm = GR + ((long long)tm * q.NR + mR) * sl;
+    for (int i = tid; i < q.nA * q.nB; i += 256) {
+      double re, im;
+      const int a = i / q.nB, c = i - a * q.nB;
+      ldc(Gt + (long long)(oA + a) * q.No + oB + c, re, im);
+      Xs[i] = mk<RT>(re, im);
+      const int d = i / q.nA, bb = i - d * q.nA;
+      ldc(Gm + (long long)(oB + d) * q.No + oA + bb, re, im);
+      Ys[i] = mk<RT>(re, im);
+    }
+    __syncthreads();
+    // Q over unordered pairs (zero outside the live pairs)
+    for (int i = tid; i < q.nppA * q.nppB; i += 256) {
+      const int p = i / q.nppB, pp = i - p * q.nppB;
+      RT qr = 0, qi = 0;
+      if (p < q.npA && pp < q.npB) {
+        const int a = ta[p], bq = tb[p], c = tc[pp], d = td[pp];
+        const int nB = q.nB, nA = q.nA;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int c1 = s ? d : c, d1 = s ? c : d;
+          if (s == 1 && c == d) break;
+          CR x = Xs[a * nB + c1], y = Ys[d1 * nA + bq];
+          qr += x.x * y.x - x.y * y.y;
+          qi += x.x * y.y + x.y * y.x;
+          if (a != bq) {
+            x = Xs[bq * nB + c1];
+            y = Ys[d1 * nA + a];
+            qr += x.x * y.x - x.y * y.y;
+            qi += x.x * y.y + x.y * y.x;
+          }
+        }
+      }
+      Qs[p * kPL + pp] = mk<RT>(qr, qi);
+    }
+    __syncthreads();
+
+    CT* Pd = P + ((long long)t * q.NR + R) * slp;
+    CT* Pm = P + ((long long)tm * q.NR + mR) * slp;
+    for (int it = w; it < nIT; it += 4) {
+      RT b1[kKA];
+#pragma unroll
+      for (int ks = 0; ks < kKA; ++ks) b1[ks] = ks < nKA ? CpA[(16 * it + li) * q.nppA + 4 * ks + lk] : RT(0);
+      typename M::acc acc2[kJT][2];
+#pragma unroll
+      for (int Jt = 0; Jt < kJT; ++Jt) acc2[Jt][0] = acc2[Jt][1] = typename M::acc{0, 0, 0, 0};
+#pragma unroll
+      for (int tt = 0; tt < kTB; ++tt) {
+        if (tt < nTB) {
+          typename M::acc acc1 = {0, 0, 0, 0};
+          const int pp = 8 * tt + row_pp;
+#pragma unroll
+          for (int ks = 0; ks < kKA; ++ks)
+            if (ks < nKA) acc1 = M::op(Qd[((4 * ks + lk) * kPL + pp) * 2 + row_part], b1[ks], acc1);
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int Jt = 0; Jt < kJT; ++Jt)
+              if (Jt < nJT) {
+                acc2[Jt][0] = M::op(a2[Jt][tt][h], acc1[2 * h], acc2[Jt][0]);
+                acc2[Jt][1] = M::op(a2[Jt][tt][h], acc1[2 * h + 1], acc2[Jt][1]);
+              }
+        }
+      }
+      const int I = 16 * it + li;
+      if (I < q.mA) {
+#pragma unroll
+        for (int Jt = 0; Jt < kJT; ++Jt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int J = 16 * Jt + M::drow(lk, j);
+            if (Jt < nJT && J < q.mB) {
+              const double re = -g * (double)acc2[Jt][0][j], im = -g * (double)acc2[Jt][1][j];
+              stc(Pd + (long long)(pA + I) * q.Np + pB + J, re, im);
+              if (t != tm) stc(Pm + (long long)(pB + J) * q.Np + pA + I, re, im);
+            }
+          }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// self-energy: one wavefront per 16 pairs p' of atom B (blockDim = 64 * nppB / 16)
+// ---------------------------------------------------------------------------
+template <class RT, class CT>
+__global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, const CT* __restrict__ WR,
+                                                 double2* __restrict__ S, const RT* __restrict__ CpA,
+                                                 const RT* __restrict__ CpB, const PairArgs q) {
+  using M = Mma<RT>;
+  typedef typename M::cplx CR;
+  __shared__ CR Xs[kMaxOrb * kMaxOrb];
+  __shared__ CR Ks[kPL * kPL];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int nthreads = blockDim.x;
+  const int nTS = q.mpA / 8, nKJ = q.mpB / 4, nMT = q.nppA / 16;
+  // first product's B operand, C~_B[J][p'], J = 4 ks + lk, p' = 16 w + li
+  RT b1[kKJ];
+#pragma unroll
+  for (int ks = 0; ks < kKJ; ++ks) b1[ks] = ks < nKJ ? CpB[(4 * ks + lk) * q.nppB + 16 * w + li] : RT(0);
+  int rg, rj;
+  M::split(li, rg, rj);
+  const int row_I = 4 * (rj >> 1) + rg, row_part = rj & 1;
+  const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+
+  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
+    long long b = blk;
+    const int iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    const int iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    const int R = (int)(b % q.NR);
+    const int t = (int)(b / q.NR);
+    const int A = q.atomsA[iA], B = q.atomsB[iB];
+    const int oA = q.orb_off[A], oB = q.orb_off[B], pA = q.pb_off[A], pB = q.pb_off[B];
+    const CT* Gt = GR + ((long long)t * q.NR + R) * sl;
+    const RT* Wb = reinterpret_cast<const RT*>(WR + ((long long)t * q.NR + R) * slp + (long long)pA * q.Np + pB);
+    for (int i = tid; i < q.nA * q.nB; i += nthreads) {
+      double re, im;
+      const int a = i / q.nB, c = i - a * q.nB;
+      ldc(Gt + (long long)(oA + a) * q.No + oB + c, re, im);
+      Xs[i] = mk<RT>(re, im);
+    }
+    typename M::acc acc2[3][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = typename M::acc{0, 0, 0, 0};
+    for (int ts = 0; ts < nTS; ++ts) {
+      // Z rows (I, part) of this tile: I = 8 ts + row_I
+      const int I = 8 * ts + row_I;
+      typename M::acc acc1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < kKJ; ++ks) {
+        if (ks < nKJ) {
+          const int J = 4 * ks + lk;
+          const RT a = (I < q.mA && J < q.mB) ? Wb[((long long)I * q.Np + J) * 2 + row_part] : RT(0);
+          acc1 = M::op(a, b1[ks], acc1);
+        }
+      }
+      // K_part[p][p'] += C~_A[I][p] Z_part[I][p'] over the K steps I = 8 ts + 4 h + lk
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int Ik = 8 * ts + 4 * h + lk;
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+          if (m < nMT) {
+            const RT a = CpA[Ik * q.nppA + 16 * m + li];
+            acc2[m][0] = M::op(a, acc1[2 * h], acc2[m][0]);
+            acc2[m][1] = M::op(a, acc1[2 * h + 1], acc2[m][1]);
+          }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+      if (m < nMT)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int p = 16 * m + M::drow(lk, j), pp = 16 * w + li;
+          Ks[p * kPL + pp] = mk<RT>((double)acc2[m][0][j], (double)acc2[m][1][j]);
+        }
+    __syncthreads();
+    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'}, summed in FP64
+    for (int o = tid; o < q.nA * q.nB; o += nthreads) {
+      const int a = o / q.nB, bb = o - a * q.nB;
+      double sr = 0, si = 0;
+      for (int ap = 0; ap < q.nA; ++ap) {
+        const int p = pair_index(a, ap, q.nA);
+        for (int bp = 0; bp < q.nB; ++bp) {
+          const CR k = Ks[p * kPL + pair_index(bb, bp, q.nB)], x = Xs[ap * q.nB + bp];
+          sr += (double)k.x * x.x - (double)k.y * x.y;
+          si += (double)k.x * x.y + (double)k.y * x.x;
+        }
+      }
+      S[((long long)t * q.NR + R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
+    }
+    __syncthreads();
+  }
+}
+
+PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, int n_half) {
+  PairArgs q;
+  q.nA = A.n;
+  q.nB = B.n;
+  q.mA = A.m;
+  q.mB = B.m;
+  q.npA = A.np;
+  q.npB = B.np;
+  q.nppA = A.np_pad;
+  q.nppB = B.np_pad;
+  q.mpA = A.m_pad;
+  q.mpB = B.m_pad;
+  q.atomsA = A.atoms_dev;
+  q.cntA = (int)A.atoms.size();
+  q.atomsB = B.atoms_dev;
+  q.cntB = (int)B.atoms.size();
+  q.orb_off = c->orb_off_dev;
+  q.pb_off = c->pb_off_dev;
+  q.minusR = c->minusR_dev;
+  q.NR = c->N_R;
+  q.n_tau = c->n_tau;
+  q.n_half = n_half;
+  q.No = c->N_orb;
+  q.Np = c->N_pb;
+  q.nblocks = (long long)n_half * c->N_R * q.cntA * q.cntB;
+  return q;
+}
+
+unsigned grid_for(long long nblocks) { return (unsigned)(nblocks < 2048 ? nblocks : 2048); }
+
+}  // namespace
+
+bool mfma_pair_ok(const SpeciesDev& A, const SpeciesDev& B) {
+  return A.np_pad <= kPL && B.np_pad <= kPL && A.m_pad <= kMP && B.m_pad <= kMP;
+}
+
+void launch_p_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
+                        double g, gw_precision p, hipStream_t s) {
+  const PairArgs q = make_args(c, A, B, (c->n_tau + 1) / 2);
+  if (q.nblocks == 0) return;
+  if (p == GW_FP64)
+    hipLaunchKernelGGL((p_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(256), 0, s,
+                       (const double2*)GR, (double2*)P, A.Cpair, B.Cpair, q, g);
+  else
+    hipLaunchKernelGGL((p_mfma<float, float2>), dim3(grid_for(q.nblocks)), dim3(256), 0, s, (const float2*)GR,
+                       (float2*)P, A.Cpair32, B.Cpair32, q, g);
+}
+
+void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
+                        const void* WR, void* S, gw_precision p, hipStream_t s) {
+  const PairArgs q = make_args(c, A, B, c->n_tau);
+  if (q.nblocks == 0) return;
+  const unsigned threads = 64u * (unsigned)(B.np_pad / 16);
+  if (p == GW_FP64)
+    hipLaunchKernelGGL((s_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
+                       (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);
+  else
+    hipLaunchKernelGGL((s_mfma<float, float2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
+                       (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+}
+
+}  // namespace gwr

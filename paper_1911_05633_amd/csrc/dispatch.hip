@@ -1,4 +1,4 @@
-// Kernel selection for the P and Sigma contractions.
+// Kernel selection for the P and Sigma contractions, one launch per species pair.
 #include <cstdlib>
 #include <cstring>
 
@@ -6,12 +6,18 @@
 
 namespace gwr {
 
-gw_status launch_p_generic(const gw_cell* c, const void* GR, void* P, double g, gw_precision p, hipStream_t s);
-gw_status launch_s_generic(const gw_cell* c, const void* GR, const void* WR, void* S, gw_precision p,
-                           hipStream_t s);
+void launch_p_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
+                           double g, gw_precision p, hipStream_t s);
+void launch_s_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
+                           const void* WR, void* S, gw_precision p, hipStream_t s);
+bool mfma_pair_ok(const SpeciesDev& A, const SpeciesDev& B);
+void launch_p_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
+                        double g, gw_precision p, hipStream_t s);
+void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
+                        const void* WR, void* S, gw_precision p, hipStream_t s);
 
-// GWR_KERNELS=generic selects the plain VALU kernels for every block shape (used by the
-// tests to check the MFMA kernels against them on the device).
+// GWR_KERNELS=generic selects the plain VALU kernels for every block shape; the tests
+// use it to check the matrix-core kernels against them on the device.
 static bool force_generic() {
   const char* v = std::getenv("GWR_KERNELS");
   return v && std::strcmp(v, "generic") == 0;
@@ -20,15 +26,33 @@ static bool force_generic() {
 gw_status launch_polarizability(const gw_cell* c, const void* GR, void* P, double g, gw_precision p,
                                 hipStream_t s) {
   if (p == GW_BF16X3) return fail(GW_ERR_UNSUPPORTED, "BF16x3 polarizability not built yet");
-  (void)force_generic();
-  return launch_p_generic(c, GR, P, g, p, s);
+  const bool gen = force_generic();
+  for (int sa = 0; sa < c->n_species; ++sa)
+    for (int sb = 0; sb < c->n_species; ++sb) {
+      const SpeciesDev &A = c->sp[sa], &B = c->sp[sb];
+      if (A.atoms.empty() || B.atoms.empty()) continue;
+      if (!gen && mfma_pair_ok(A, B) && mfma_pair_ok(B, A))
+        launch_p_mfma_pair(c, A, B, GR, P, g, p, s);
+      else
+        launch_p_generic_pair(c, A, B, GR, P, g, p, s);
+    }
+  return check_launch("polarizability");
 }
 
 gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, void* S, gw_precision p,
                              hipStream_t s) {
   if (p == GW_BF16X3) return fail(GW_ERR_UNSUPPORTED, "BF16x3 self-energy not built yet");
-  (void)force_generic();
-  return launch_s_generic(c, GR, WR, S, p, s);
+  const bool gen = force_generic();
+  for (int sa = 0; sa < c->n_species; ++sa)
+    for (int sb = 0; sb < c->n_species; ++sb) {
+      const SpeciesDev &A = c->sp[sa], &B = c->sp[sb];
+      if (A.atoms.empty() || B.atoms.empty()) continue;
+      if (!gen && mfma_pair_ok(A, B))
+        launch_s_mfma_pair(c, A, B, GR, WR, S, p, s);
+      else
+        launch_s_generic_pair(c, A, B, GR, WR, S, p, s);
+    }
+  return check_launch("self-energy");
 }
 
 }  // namespace gwr

@@ -20,7 +20,7 @@ constexpr int kMaxPairs = kMaxOrb * (kMaxOrb + 1) / 2;  // 136
 struct SpeciesDev {
   int n = 0, m = 0;     // orbitals, product functions
   int np = 0;           // unordered orbital pairs n(n+1)/2
-  int np_pad = 0;       // np rounded up to a multiple of 8
+  int np_pad = 0;       // np rounded up to a multiple of 16
   int m_pad = 0;        // m rounded up to a multiple of 16
   double* C = nullptr;          // [m][n][n] FP64 (plain layout)
   float* C32 = nullptr;         // [m][n][n] FP32

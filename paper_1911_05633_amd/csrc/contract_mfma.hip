@@ -113,6 +113,9 @@ struct PairArgs {
 // ---------------------------------------------------------------------------
 // polarizability
 // ---------------------------------------------------------------------------
+constexpr int kQS = 56;      // LDS row stride of Q (complex): 4 consecutive rows land 32 banks apart
+constexpr int kCS = kPL + 1; // LDS row stride of C~_B (real): 16 consecutive rows hit distinct banks
+
 template <class RT, class CT>
 __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* __restrict__ P,
                                                  const RT* __restrict__ CpA, const RT* __restrict__ CpB,
@@ -120,52 +123,72 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   using M = Mma<RT>;
   typedef typename M::cplx CR;
   __shared__ CR Xs[kMaxOrb * kMaxOrb], Ys[kMaxOrb * kMaxOrb];
-  __shared__ CR Qs[kPL * kPL];
+  __shared__ CR Qs[kPL * kQS];
+  __shared__ RT Cb[kMP * kCS];
   __shared__ unsigned char ta[kPL], tb[kPL], tc[kPL], td[kPL];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   if (tid < q.npA) pair_of(tid, q.nA, ta[tid], tb[tid]);
   if (tid < q.npB) pair_of(tid, q.nB, tc[tid], td[tid]);
+  for (int i = tid; i < q.mpB * q.nppB; i += 256) {
+    const int J = i / q.nppB, pp = i - J * q.nppB;
+    Cb[J * kCS + pp] = CpB[i];
+  }
   const int nKA = q.nppA / 4, nTB = q.nppB / 8, nJT = (q.mB + 15) / 16, nIT = q.mpA / 16;
-
-  // second product's A operand, C~_B[J][p'], J = 16 Jt + li, p' = 8 t + 4 h + lk
-  RT a2[kJT][kTB][2];
-#pragma unroll
-  for (int Jt = 0; Jt < kJT; ++Jt)
-#pragma unroll
-    for (int t = 0; t < kTB; ++t)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        a2[Jt][t][h] = (Jt < nJT && t < nTB) ? CpB[(16 * Jt + li) * q.nppB + 8 * t + 4 * h + lk] : RT(0);
   int rg, rj;
   M::split(li, rg, rj);
   const int row_pp = 4 * (rj >> 1) + rg, row_part = rj & 1;
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
   const RT* Qd = reinterpret_cast<const RT*>(Qs);
-  __syncthreads();
-
-  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
-    long long b = blk;
+  struct Blk {
+    int t, R, A, B;
+  };
+  auto decode = [&](long long b) {
+    Blk o;
     const int iB = (int)(b % q.cntB);
     b /= q.cntB;
     const int iA = (int)(b % q.cntA);
     b /= q.cntA;
-    const int R = (int)(b % q.NR);
-    const int t = (int)(b / q.NR);
-    const int A = q.atomsA[iA], B = q.atomsB[iB];
+    o.R = (int)(b % q.NR);
+    o.t = (int)(b / q.NR);
+    o.A = q.atomsA[iA];
+    o.B = q.atomsB[iB];
+    return o;
+  };
+  // the X and Y tiles of the next block are loaded into registers (one element per thread,
+  // n_A n_B <= 81 < 256) while the current block is on the matrix cores
+  CR xr, yr;
+  auto fetch = [&](const Blk& k) {
+    const int tid2 = tid;
+    double re = 0, im = 0;
+    if (tid2 < q.nA * q.nB) {
+      const int a = tid2 / q.nB, c = tid2 - a * q.nB;
+      ldc(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
+          re, im);
+    }
+    xr = mk<RT>(re, im);
+    re = im = 0;
+    if (tid2 < q.nA * q.nB) {
+      const int d = tid2 / q.nA, bb = tid2 - d * q.nA;
+      ldc(GR + ((long long)(q.n_tau - 1 - k.t) * q.NR + q.minusR[k.R]) * sl +
+              (long long)(q.orb_off[k.B] + d) * q.No + q.orb_off[k.A] + bb,
+          re, im);
+    }
+    yr = mk<RT>(re, im);
+  };
+  if (blockIdx.x < q.nblocks) fetch(decode(blockIdx.x));
+  __syncthreads();
+
+  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
+    const Blk k = decode(blk);
+    const int t = k.t, R = k.R;
     const int tm = q.n_tau - 1 - t, mR = q.minusR[R];
-    const int oA = q.orb_off[A], oB = q.orb_off[B], pA = q.pb_off[A], pB = q.pb_off[B];
-    const CT* Gt = GR + ((long long)t * q.NR + R) * sl;
-    const CT* Gm = GR + ((long long)tm * q.NR + mR) * sl;
-    for (int i = tid; i < q.nA * q.nB; i += 256) {
-      double re, im;
-      const int a = i / q.nB, c = i - a * q.nB;
-      ldc(Gt + (long long)(oA + a) * q.No + oB + c, re, im);
-      Xs[i] = mk<RT>(re, im);
-      const int d = i / q.nA, bb = i - d * q.nA;
-      ldc(Gm + (long long)(oB + d) * q.No + oA + bb, re, im);
-      Ys[i] = mk<RT>(re, im);
+    const int pA = q.pb_off[k.A], pB = q.pb_off[k.B];
+    if (tid < q.nA * q.nB) {
+      Xs[tid] = xr;
+      Ys[tid] = yr;
     }
     __syncthreads();
+    if (blk + gridDim.x < q.nblocks) fetch(decode(blk + gridDim.x));
     // Q over unordered pairs (zero outside the live pairs)
     for (int i = tid; i < q.nppA * q.nppB; i += 256) {
       const int p = i / q.nppB, pp = i - p * q.nppB;
@@ -188,7 +211,7 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
           }
         }
       }
-      Qs[p * kPL + pp] = mk<RT>(qr, qi);
+      Qs[p * kQS + pp] = mk<RT>(qr, qi);
     }
     __syncthreads();
 
@@ -201,22 +224,31 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
       typename M::acc acc2[kJT][2];
 #pragma unroll
       for (int Jt = 0; Jt < kJT; ++Jt) acc2[Jt][0] = acc2[Jt][1] = typename M::acc{0, 0, 0, 0};
+      // first product for tile tt: rows (p', part) of Q^T against C~_A^T
+      auto gemm1 = [&](int tt) {
+        typename M::acc a1 = {0, 0, 0, 0};
+        const int pp = 8 * tt + row_pp;
+#pragma unroll
+        for (int ks = 0; ks < kKA; ++ks)
+          if (ks < nKA) a1 = M::op(Qd[((4 * ks + lk) * kQS + pp) * 2 + row_part], b1[ks], a1);
+        return a1;
+      };
+      typename M::acc acc1 = gemm1(0);
 #pragma unroll
       for (int tt = 0; tt < kTB; ++tt) {
         if (tt < nTB) {
-          typename M::acc acc1 = {0, 0, 0, 0};
-          const int pp = 8 * tt + row_pp;
-#pragma unroll
-          for (int ks = 0; ks < kKA; ++ks)
-            if (ks < nKA) acc1 = M::op(Qd[((4 * ks + lk) * kPL + pp) * 2 + row_part], b1[ks], acc1);
+          typename M::acc nxt = {0, 0, 0, 0};
+          if (tt + 1 < nTB) nxt = gemm1(tt + 1);
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int Jt = 0; Jt < kJT; ++Jt)
               if (Jt < nJT) {
-                acc2[Jt][0] = M::op(a2[Jt][tt][h], acc1[2 * h], acc2[Jt][0]);
-                acc2[Jt][1] = M::op(a2[Jt][tt][h], acc1[2 * h + 1], acc2[Jt][1]);
+                const RT a = Cb[(16 * Jt + li) * kCS + 8 * tt + 4 * h + lk];
+                acc2[Jt][0] = M::op(a, acc1[2 * h], acc2[Jt][0]);
+                acc2[Jt][1] = M::op(a, acc1[2 * h + 1], acc2[Jt][1]);
               }
+          acc1 = nxt;
         }
       }
       const int I = 16 * it + li;
@@ -239,96 +271,166 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
 }
 
 // ---------------------------------------------------------------------------
-// self-energy: one wavefront per 16 pairs p' of atom B (blockDim = 64 * nppB / 16)
+// self-energy.  192 threads: wavefront w owns the 16 pairs p' = 16 w .. 16 w + 15 of
+// atom B (idle in the matrix phase if 16 w >= np_pad(B)).  W^R(tau)[A, B] streams
+// through a double-buffered LDS tile of 16 rows (I) with coalesced loads; the next
+// tile is fetched into registers while the current one is multiplied.  The
+// first product runs separately on Re W and Im W (rows I), so every 16-byte W
+// element read from LDS feeds two MFMAs.
 // ---------------------------------------------------------------------------
+constexpr int kWS = kMP + 1;                     // W tile row stride (complex)
+constexpr int kKS = kPL + 1;                     // K row stride (complex)
+constexpr int kUnf = 9 * 9 * 9;                  // (a, a', b) partial sums for n <= 9
+constexpr int kSThreads = 192;
+constexpr int kWPT = (16 * kMP + kSThreads - 1) / kSThreads;
+
 template <class RT, class CT>
 __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, const CT* __restrict__ WR,
                                                  double2* __restrict__ S, const RT* __restrict__ CpA,
                                                  const RT* __restrict__ CpB, const PairArgs q) {
   using M = Mma<RT>;
   typedef typename M::cplx CR;
-  __shared__ CR Xs[kMaxOrb * kMaxOrb];
-  __shared__ CR Ks[kPL * kPL];
+  constexpr size_t kWbytes = 2 * 16 * kWS * sizeof(CR);
+  constexpr size_t kKbytes = kPL * kKS * sizeof(CR) + kUnf * sizeof(double2);
+  __shared__ __align__(16) unsigned char U[kWbytes > kKbytes ? kWbytes : kKbytes];
+  __shared__ CR Xs[81];
+  __shared__ RT Ca[kMP * kPL];
+  __shared__ unsigned char pidA[81], pidB[81];
+  CR* Wb = reinterpret_cast<CR*>(U);
+  CR* Ks = reinterpret_cast<CR*>(U);
+  double2* Pp = reinterpret_cast<double2*>(U + kPL * kKS * sizeof(CR));
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
-  const int nthreads = blockDim.x;
-  const int nTS = q.mpA / 8, nKJ = q.mpB / 4, nMT = q.nppA / 16;
-  // first product's B operand, C~_B[J][p'], J = 4 ks + lk, p' = 16 w + li
+  const int nIT = q.mpA / 16, nKJ = q.mpB / 4, nMT = q.nppA / 16;
+  const bool mm = 16 * w < q.nppB;  // this wavefront has pairs of B
+  for (int i = tid; i < q.nA * q.nA; i += kSThreads) pidA[i] = (unsigned char)pair_index(i / q.nA, i % q.nA, q.nA);
+  for (int i = tid; i < q.nB * q.nB; i += kSThreads) pidB[i] = (unsigned char)pair_index(i / q.nB, i % q.nB, q.nB);
   RT b1[kKJ];
 #pragma unroll
-  for (int ks = 0; ks < kKJ; ++ks) b1[ks] = ks < nKJ ? CpB[(4 * ks + lk) * q.nppB + 16 * w + li] : RT(0);
-  int rg, rj;
-  M::split(li, rg, rj);
-  const int row_I = 4 * (rj >> 1) + rg, row_part = rj & 1;
+  for (int ks = 0; ks < kKJ; ++ks) b1[ks] = (mm && ks < nKJ) ? CpB[(4 * ks + lk) * q.nppB + 16 * w + li] : RT(0);
+  for (int i = tid; i < q.mpA * q.nppA; i += kSThreads) Ca[i] = CpA[i];
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
 
-  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
-    long long b = blk;
+  struct Blk {
+    int t, R, A, B;
+  };
+  auto decode = [&](long long b) {
+    Blk o;
     const int iB = (int)(b % q.cntB);
     b /= q.cntB;
     const int iA = (int)(b % q.cntA);
     b /= q.cntA;
-    const int R = (int)(b % q.NR);
-    const int t = (int)(b / q.NR);
-    const int A = q.atomsA[iA], B = q.atomsB[iB];
-    const int oA = q.orb_off[A], oB = q.orb_off[B], pA = q.pb_off[A], pB = q.pb_off[B];
-    const CT* Gt = GR + ((long long)t * q.NR + R) * sl;
-    const RT* Wb = reinterpret_cast<const RT*>(WR + ((long long)t * q.NR + R) * slp + (long long)pA * q.Np + pB);
-    for (int i = tid; i < q.nA * q.nB; i += nthreads) {
-      double re, im;
-      const int a = i / q.nB, c = i - a * q.nB;
-      ldc(Gt + (long long)(oA + a) * q.No + oB + c, re, im);
-      Xs[i] = mk<RT>(re, im);
+    o.R = (int)(b % q.NR);
+    o.t = (int)(b / q.NR);
+    o.A = q.atomsA[iA];
+    o.B = q.atomsB[iB];
+    return o;
+  };
+  CR wreg[kWPT];
+  auto fetch = [&](const Blk& k, int it) {
+    const CT* Wt = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)q.pb_off[k.A] * q.Np + q.pb_off[k.B];
+#pragma unroll
+    for (int u = 0; u < kWPT; ++u) {
+      const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP, I = 16 * it + r;
+      double re = 0, im = 0;
+      if (r < 16 && I < q.mA && c < q.mB) ldc(Wt + (long long)I * q.Np + c, re, im);
+      wreg[u] = mk<RT>(re, im);
     }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < kWPT; ++u) {
+      const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP;
+      if (r < 16) Wb[(buf * 16 + r) * kWS + c] = wreg[u];
+    }
+  };
+
+  CR xr;
+  auto fetch_x = [&](const Blk& k) {
+    double re = 0, im = 0;
+    if (tid < q.nA * q.nB) {
+      const int a = tid / q.nB, c = tid - a * q.nB;
+      ldc(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
+          re, im);
+    }
+    xr = mk<RT>(re, im);
+  };
+  if (blockIdx.x < q.nblocks) {
+    fetch(decode(blockIdx.x), 0);
+    fetch_x(decode(blockIdx.x));
+  }
+  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
+    const Blk k = decode(blk);
+    const int oA = q.orb_off[k.A], oB = q.orb_off[k.B];
+    if (tid < q.nA * q.nB) Xs[tid] = xr;
+    stash(0);
+    __syncthreads();
     typename M::acc acc2[3][2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = typename M::acc{0, 0, 0, 0};
-    for (int ts = 0; ts < nTS; ++ts) {
-      // Z rows (I, part) of this tile: I = 8 ts + row_I
-      const int I = 8 * ts + row_I;
-      typename M::acc acc1 = {0, 0, 0, 0};
+    for (int it = 0; it < nIT; ++it) {
+      if (it + 1 < nIT) fetch(k, it + 1);
+      if (mm) {
+        const CR* Wt = Wb + (it & 1) * 16 * kWS;
+        typename M::acc zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
 #pragma unroll
-      for (int ks = 0; ks < kKJ; ++ks) {
-        if (ks < nKJ) {
-          const int J = 4 * ks + lk;
-          const RT a = (I < q.mA && J < q.mB) ? Wb[((long long)I * q.Np + J) * 2 + row_part] : RT(0);
-          acc1 = M::op(a, b1[ks], acc1);
-        }
-      }
-      // K_part[p][p'] += C~_A[I][p] Z_part[I][p'] over the K steps I = 8 ts + 4 h + lk
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int Ik = 8 * ts + 4 * h + lk;
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-          if (m < nMT) {
-            const RT a = CpA[Ik * q.nppA + 16 * m + li];
-            acc2[m][0] = M::op(a, acc1[2 * h], acc2[m][0]);
-            acc2[m][1] = M::op(a, acc1[2 * h + 1], acc2[m][1]);
+        for (int ks = 0; ks < kKJ; ++ks)
+          if (ks < nKJ) {
+            const CR wv = Wt[li * kWS + 4 * ks + lk];
+            zr = M::op(wv.x, b1[ks], zr);
+            zi = M::op(wv.y, b1[ks], zi);
           }
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-      if (m < nMT)
+        // K_part[p][p'] += C~_A[I][p] Z_part[I][p'], K steps I = 16 it + drow(lk, j)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int p = 16 * m + M::drow(lk, j), pp = 16 * w + li;
-          Ks[p * kPL + pp] = mk<RT>((double)acc2[m][0][j], (double)acc2[m][1][j]);
-        }
-    __syncthreads();
-    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'}, summed in FP64
-    for (int o = tid; o < q.nA * q.nB; o += nthreads) {
-      const int a = o / q.nB, bb = o - a * q.nB;
-      double sr = 0, si = 0;
-      for (int ap = 0; ap < q.nA; ++ap) {
-        const int p = pair_index(a, ap, q.nA);
-        for (int bp = 0; bp < q.nB; ++bp) {
-          const CR k = Ks[p * kPL + pair_index(bb, bp, q.nB)], x = Xs[ap * q.nB + bp];
-          sr += (double)k.x * x.x - (double)k.y * x.y;
-          si += (double)k.x * x.y + (double)k.y * x.x;
+          const int Ik = 16 * it + M::drow(lk, j);
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            if (m < nMT) {
+              const RT a = Ca[Ik * q.nppA + 16 * m + li];
+              acc2[m][0] = M::op(a, zr[j], acc2[m][0]);
+              acc2[m][1] = M::op(a, zi[j], acc2[m][1]);
+            }
         }
       }
-      S[((long long)t * q.NR + R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
+      if (it + 1 < nIT) stash((it + 1) & 1);
+      __syncthreads();
+    }
+    if (blk + gridDim.x < q.nblocks) {
+      const Blk kn = decode(blk + gridDim.x);
+      fetch(kn, 0);
+      fetch_x(kn);
+    }
+    if (mm) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        if (m < nMT)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            Ks[(16 * m + M::drow(lk, j)) * kKS + 16 * w + li] = mk<RT>((double)acc2[m][0][j], (double)acc2[m][1][j]);
+    }
+    __syncthreads();
+    // partial sums over b' for every (a, a', b), in FP64
+    for (int i = tid; i < q.nA * q.nA * q.nB; i += kSThreads) {
+      const int ap = i / (q.nA * q.nB), r = i - ap * q.nA * q.nB, a = r / q.nB, bb = r - a * q.nB;
+      const CR* Kr = Ks + pidA[a * q.nA + ap] * kKS;
+      double sr = 0, si = 0;
+      for (int bp = 0; bp < q.nB; ++bp) {
+        const CR kv = Kr[pidB[bb * q.nB + bp]], x = Xs[ap * q.nB + bp];
+        sr += (double)kv.x * x.x - (double)kv.y * x.y;
+        si += (double)kv.x * x.y + (double)kv.y * x.x;
+      }
+      Pp[i] = make_double2(sr, si);
+    }
+    __syncthreads();
+    for (int o = tid; o < q.nA * q.nB; o += kSThreads) {
+      double sr = 0, si = 0;
+      for (int ap = 0; ap < q.nA; ++ap) {
+        const double2 v = Pp[ap * q.nA * q.nB + o];
+        sr += v.x;
+        si += v.y;
+      }
+      const int a = o / q.nB, bb = o - a * q.nB;
+      S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
     }
     __syncthreads();
   }
@@ -386,7 +488,7 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
                         const void* WR, void* S, gw_precision p, hipStream_t s) {
   const PairArgs q = make_args(c, A, B, c->n_tau);
   if (q.nblocks == 0) return;
-  const unsigned threads = 64u * (unsigned)(B.np_pad / 16);
+  const unsigned threads = kSThreads;
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);

@@ -152,6 +152,117 @@ __global__ __launch_bounds__(256) void drain_mfma(const double2* __restrict__ T,
   }
 }
 
+// Persistent variant with T resident in LDS and the complex product done as three
+// real GEMMs (t1 = Tr yr, t2 = Ti yi, t3 = (Tr + Ti)(yr + yi); re = t1 - t2,
+// im = t3 - t1 - t2), 3/4 of the MFMA work of the 2x2 block form.  M is the
+// frequency (MT tiles of 16), K = tau (steps of 4), N = 16 columns per wavefront.
+// A chunk is CB consecutive matrix elements (CB * 16 bytes contiguous per (tau, R)
+// row, 256 bytes for complex128 when CB = 16) times the N_R lattice vectors; the
+// next chunk is loaded into registers while the current one is on the matrix cores.
+// LDS: T [16 MT][nt4 + 1] complex and y [nt4][16 * waves] complex, nt4 = n_tau
+// rounded up to 4.
+constexpr int kPF = 16;  // prefetched complex values per thread (upper bound)
+
+template <int N1, int N2, int N3, int MT, class TI, class TO>
+__global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T, int n_omega, int n_tau,
+                                                   const TI* in, TO* out, long long n2, int CB,
+                                                   long long nchunks) {
+  constexpr int NR = N1 * N2 * N3;
+  extern __shared__ double2 lds[];
+  const int tid = threadIdx.x, nthr = blockDim.x, waves = nthr >> 6;
+  const int nt4 = (n_tau + 3) & ~3, ld_t = nt4 + 1, ncp = 16 * waves;
+  double2* Ts = lds;                      // [16 MT][ld_t]
+  double2* y = lds + 16 * MT * ld_t;      // [nt4][ncp]
+  for (int i = tid; i < 16 * MT * ld_t; i += nthr) {
+    const int m = i / ld_t, t = i - m * ld_t;
+    Ts[i] = (m < n_omega && t < n_tau) ? T[(long long)m * n_tau + t] : make_double2(0.0, 0.0);
+  }
+  const int ncol = NR * CB;
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int col = 16 * w + li;
+  const int ksn = nt4 / 4;
+  const int items = nt4 * ncp;  // LDS slots of one chunk
+  double pr[kPF], pi[kPF];
+  auto fetch = [&](long long ch) {
+    const long long e0 = ch * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      const int idx = tid + nthr * u;
+      double a = 0, b = 0;
+      if (idx < items) {
+        const int t = idx / ncp, rc = idx - t * ncp;
+        if (t < n_tau && rc < ncol) {
+          const int R = rc / CB, c = rc - R * CB;
+          if (c < cb) ldc(in + ((long long)t * NR + R) * n2 + e0 + c, a, b);
+        }
+      }
+      pr[u] = a;
+      pi[u] = b;
+    }
+  };
+  if (blockIdx.x < nchunks) fetch(blockIdx.x);
+  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const long long e0 = ch * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+    __syncthreads();  // T staged / previous chunk's matrix phase done with y
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      const int idx = tid + nthr * u;
+      if (idx < items) y[idx] = make_double2(pr[u], pi[u]);
+    }
+    __syncthreads();
+    if constexpr (NR > 1) {
+      for (int idx = tid; idx < n_tau * CB; idx += nthr) {
+        const int t = idx / CB, c = idx - t * CB;
+        double re[NR], im[NR];
+#pragma unroll
+        for (int R = 0; R < NR; ++R) {
+          const double2 v = y[t * ncp + R * CB + c];
+          re[R] = v.x;
+          im[R] = v.y;
+        }
+        dft_pass_minus<N1 * N2, N3, 1>(re, im);
+        dft_pass_minus<N1, N2, N3>(re, im);
+        dft_pass_minus<1, N1, N2 * N3>(re, im);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) y[t * ncp + q * CB + c] = make_double2(re[q], im[q]);
+      }
+      __syncthreads();
+    }
+    if (ch + gridDim.x < nchunks) fetch(ch + gridDim.x);  // in flight during the matrix phase
+    d4 t1[MT], t2[MT], t3[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) t1[i] = t2[i] = t3[i] = d4{0, 0, 0, 0};
+    for (int ks = 0; ks < ksn; ++ks) {
+      const int tau = 4 * ks + lk;
+      const double2 yv = y[tau * ncp + col];
+      const double ys = yv.x + yv.y;
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        const double2 tv = Ts[(16 * i + li) * ld_t + tau];
+        t1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.x, yv.x, t1[i], 0, 0, 0);
+        t2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.y, yv.y, t2[i], 0, 0, 0);
+        t3[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.x + tv.y, ys, t3[i], 0, 0, 0);
+      }
+    }
+    // D fragment: register j of lane group lk is frequency 16 i + lk + 4 j, column `col`
+    if (col < ncol) {
+      const int q = col / CB, c = col - q * CB;
+      if (c < cb) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int m = 16 * i + lk + 4 * j;
+            if (m < n_omega)
+              stc(out + ((long long)m * NR + q) * n2 + e0 + c, t1[i][j] - t2[i][j], t3[i][j] - t1[i][j] - t2[i][j]);
+          }
+      }
+    }
+  }
+}
+
 // Plain FP64 VALU transform for sizes outside the MFMA kernel's range (tau <= 256).
 template <class TI, class TO>
 __global__ __launch_bounds__(256) void tau2omega_valu(const double2* __restrict__ T, int n_omega, int n_tau,
@@ -179,9 +290,39 @@ __global__ __launch_bounds__(256) void tau2omega_valu(const double2* __restrict_
   }
 }
 
+template <int N1, int N2, int N3, int MT, class TI, class TO>
+void run_drain_3m(const double2* T, int n_omega, int n_tau, const TI* in, TO* out, long long n2, size_t lds,
+                  int waves, int CB, hipStream_t s) {
+  const long long nchunks = (n2 + CB - 1) / CB;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)drain_3m<N1, N2, N3, MT, TI, TO>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const long long grid = nchunks < 256 ? nchunks : 256;
+  hipLaunchKernelGGL((drain_3m<N1, N2, N3, MT, TI, TO>), dim3((unsigned)grid), dim3(64 * waves), lds, s, T,
+                     n_omega, n_tau, in, out, n2, CB, nchunks);
+}
+
 template <int N1, int N2, int N3, class TI, class TO>
 void run_drain(const double2* T, int n_omega, int n_tau, const TI* in, TO* out, long long n2, hipStream_t s) {
   constexpr int NR = N1 * N2 * N3;
+  // persistent 3M kernel: the widest chunk (<= 128 columns) whose T + y fit in LDS and
+  // whose prefetch fits the per-thread register budget
+  const int MT = (n_omega + 15) / 16;
+  const int nt4 = (n_tau + 3) & ~3;
+  for (int cols = 128; cols >= 16 && MT <= 4; cols /= 2) {
+    const int CB = NR >= cols ? 1 : cols / NR;
+    const int waves = (NR * CB + 15) / 16;
+    if (waves > 8) continue;
+    const size_t lds = (size_t)(16 * MT * (nt4 + 1) + nt4 * 16 * waves) * sizeof(double2);
+    if (lds > 160 * 1024 || nt4 * 16 * waves > kPF * 64 * waves) continue;
+    switch (MT) {
+      case 1: run_drain_3m<N1, N2, N3, 1>(T, n_omega, n_tau, in, out, n2, lds, waves, CB, s); return;
+      case 2: run_drain_3m<N1, N2, N3, 2>(T, n_omega, n_tau, in, out, n2, lds, waves, CB, s); return;
+      case 3: run_drain_3m<N1, N2, N3, 3>(T, n_omega, n_tau, in, out, n2, lds, waves, CB, s); return;
+      case 4: run_drain_3m<N1, N2, N3, 4>(T, n_omega, n_tau, in, out, n2, lds, waves, CB, s); return;
+      default: break;
+    }
+  }
   const int CB = kDrainCols / NR;
   const unsigned blocks = (unsigned)((n2 + CB - 1) / CB);
   const size_t lds = (size_t)((n_tau + 1) / 2 * 2) * kDrainCols * sizeof(double2);

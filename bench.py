@@ -5,9 +5,13 @@
 A step is the whole path on one synthetic cell with inputs resident in HBM:
     G(k,tau) -k2r-> G(R,tau) -> P (Eq. 5) and Sigma (Eq. 8, with W(R,tau))
     -> drain (R->k, tau->Matsubara) of P and of Sigma -> electron count.
-The metric is the algorithmic P + Sigma GFLOP/s of the whole step.  One JSON
-line is printed with a roofline entry for the dominant kernel (timed with
-events on the launch stream) and the CPU oracle timed on a bounded sample.
+The metric is the algorithmic P + Sigma GFLOP/s of the whole step.  The default
+(mixed) path stores G, W, P as complex64 and runs the contractions on the FP32
+matrix cores; the lattice and Matsubara transforms, the Sigma orbital sums and
+the electron count are FP64.  The plain FP64 path is timed after it for the
+speedup.  One JSON line is printed with a roofline entry for the dominant kernel
+(timed with events on the launch stream) and the CPU oracle timed on a bounded
+sample, whose outputs also give the error of the timed path.
 """
 import argparse
 import json
@@ -84,7 +88,8 @@ def run_step(g, cell, d, spec, prec, ev=None):
         lambda: g.gw_self_energy(cell, d["GR"], d["W"], d["S"], prec=prec),
         lambda: g.gw_drain(cell, d["TP"], d["P"], d["P"], basis=1),
         lambda: g.gw_drain(cell, d["TS"], d["S"], d["S"], basis=0),
-        lambda: g.gw_density(cell, d["GR"], spec.spin, d["n"]),
+        (lambda: g.gw_density(cell, d["GR"], spec.spin, d["n"], space=0)) if prec == "fp64" else
+        (lambda: g.gw_density(cell, d["Gk"], spec.spin, d["n"], space=1)),
     ]
     for i, f in enumerate(calls):
         if ev is not None:
@@ -112,31 +117,68 @@ def kernel_roofs(spec, prec, fp, fs):
     return roofs
 
 
-def cpu_baseline(spec, d, fp, fs, log):
+def cpu_baseline(spec, d, fp, fs, log, g, cell, prec):
     """The FP64 oracle on a bounded sample: P^q(tau) for one (tau, q) and Sigma^k(tau) for one
-    (tau, k) of the same cell; scaled to the metric as (fraction of the step's work) / time."""
+    (tau, k) of the same cell; scaled to the metric as (fraction of the step's work) / time.
+    The same slices of the timed GPU path (recomputed, then R -> k) give its error."""
+    import torch
     import oracle
-    import synthcell as sc
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
-    t = spec.n_tau // 3
+    t, q = spec.n_tau // 3, 1
     t0 = time.perf_counter()
-    oracle.polarizability_q(d["Gk_h"], spec, d["C"], spec.spin, taus=[t], qs=[1])
+    Pq = oracle.polarizability_q(d["Gk_h"], spec, d["C"], spec.spin, taus=[t], qs=[q])[0, 0]
     tp = time.perf_counter() - t0
     WR = {t: (d["et"][t] * d["sR"][:, None, None] * d["A"][None]).astype(np.complex128)}
     t0 = time.perf_counter()
-    oracle.self_energy_k(d["Gk_h"], WR, spec, d["C"], taus=[t], ks=[1])
+    Sk = oracle.self_energy_k(d["Gk_h"], WR, spec, d["C"], taus=[t], ks=[q])[0, 0]
     ts = time.perf_counter() - t0
     frac = 1.0 / (spec.n_tau * spec.N_R)  # one (tau, q) slice of the whole P (and of Sigma)
     work = frac * (fp + fs) * spec.n_tau * spec.N_R
     log(f"cpu oracle sample: P {tp:.1f}s, Sigma {ts:.1f}s")
-    return {"value": work / (tp + ts) / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"k-space FP64 oracle: P^q(tau) for 1 tau x 1 q and Sigma^k(tau) for 1 tau x 1 k of "
-                      f"the {spec.n_atoms}-atom cell (each a 1/{spec.n_tau * spec.N_R} share of the step's "
-                      f"P or Sigma output); {tp + ts:.1f} s"}
+    # the timed path's outputs on the same slices
+    g.gw_fourier_k2r(cell, d["Gk"], d["GR"], basis=0)
+    g.gw_polarizability(cell, d["GR"], d["P"], spec.spin, prec=prec)
+    g.gw_self_energy(cell, d["GR"], d["W"], d["S"], prec=prec)
+    g.gw_fourier_r2k(cell, d["P"], d["P"], basis=1)
+    g.gw_fourier_r2k(cell, d["S"], d["S"], basis=0)
+    torch.cuda.synchronize()
+    Pg = d["P"][t, q].cpu().numpy().astype(np.complex128)
+    Sg = d["S"][t, q].cpu().numpy()
+    err = {}
+    for name, a, b in (("P", Pg, Pq), ("Sigma", Sg, Sk)):
+        mx = float(np.max(np.abs(a - b)))
+        err[name] = {"max_abs": mx, "rel": mx / float(np.max(np.abs(b)))}
+    log(f"error vs oracle on the sampled slices: {err}")
+    return ({"value": work / (tp + ts) / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+             "sample": f"k-space FP64 oracle: P^q(tau) for 1 tau x 1 q and Sigma^k(tau) for 1 tau x 1 k of "
+                       f"the {spec.n_atoms}-atom cell (each a 1/{spec.n_tau * spec.N_R} share of the step's "
+                       f"P or Sigma output); {tp + ts:.1f} s"}, err)
+
+
+def time_path(g, spec, prec, steps, warmup, torch, log):
+    """Build the inputs for one precision, time `steps` steps; returns (d, cell, ms, per-kernel ms)."""
+    d = build_inputs(spec, prec, torch, log)
+    cell = g.Cell.from_spec(spec, d["C"])
+    for _ in range(warmup):
+        run_step(g, cell, d, spec, prec)
+    torch.cuda.synchronize()
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in KERNELS]
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        run_step(g, cell, d, spec, prec, ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = {k: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(steps)]))
+           for i, k in enumerate(KERNELS)}
+    log(f"{prec}: {wall / steps * 1e3:.2f} ms/step; per-kernel ms: " +
+        ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
+    return d, cell, wall / steps * 1e3, per
 
 
 def main():
@@ -145,8 +187,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"],
+                    help="contraction arithmetic: fp32 = the mixed path (default), fp64 = plain FP64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -163,25 +207,8 @@ def main():
     spec = sc.config(args.config)
     log(f"config {args.config}: {spec.name}, {spec.n_atoms} atoms, N_orb {spec.N_orb}, N_pb {spec.N_pb}, "
         f"N_R {spec.N_R}, n_tau {spec.n_tau}, prec {args.prec}")
-    d = build_inputs(spec, args.prec, torch, log)
-    cell = g.Cell.from_spec(spec, d["C"])
     fp, fs = pair_flops(spec)
-    for _ in range(args.warmup):
-        run_step(g, cell, d, spec, args.prec)
-    torch.cuda.synchronize()
-    log("warmup done")
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in KERNELS]
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        run_step(g, cell, d, spec, args.prec, ev[s])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per = {k: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]))
-           for i, k in enumerate(KERNELS)}
-    log("per-kernel ms: " + ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
-    ms = wall / args.steps * 1e3
+    d, cell, ms, per = time_path(g, spec, args.prec, args.steps, args.warmup, torch, log)
     total_flops = (fp + fs) * spec.n_tau * spec.N_R
     roofs = kernel_roofs(spec, args.prec, fp, fs)
     dom = max(per, key=per.get)
@@ -190,6 +217,7 @@ def main():
     unit = "GB/s" if bound == "hbm" else "TFLOP/s"
     scale = 1e9 if bound == "hbm" else 1e12
     n_val = float(d["n"].cpu()[0])
+    dtype = {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.prec]
     out = {
         "metric": "P+Sigma GFLOP/s per scGW step (72-atom Si-like cell); frac of MFMA peak in roofline",
         "value": total_flops / (ms * 1e-3) / 1e9,
@@ -201,7 +229,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.prec],
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{spec.name}: {spec.n_atoms} atoms, n_orb {spec.n_orb}, n_pb {spec.n_pb}, "
                                f"mesh {'x'.join(map(str, spec.mesh))}, n_tau {spec.n_tau}, beta {spec.beta}",
@@ -210,7 +238,16 @@ def main():
                      "unit": unit, "frac": achieved / peak, "traffic": None},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(spec, d, fp, fs, log)
+        out["cpu_baseline"], out["config"]["error_vs_oracle"] = cpu_baseline(spec, d, fp, fs, log, g, cell,
+                                                                             args.prec)
+    if args.prec != "fp64" and not args.no_fp64:
+        del d, cell
+        torch.cuda.empty_cache()
+        d64, cell64, ms64, per64 = time_path(g, spec, "fp64", max(1, min(args.steps, 3)), 1, torch, log)
+        out["config"]["fp64_ms_per_step"] = ms64
+        out["config"]["fp64_per_kernel_ms"] = per64
+        out["config"]["speedup_vs_fp64"] = ms64 / ms
+        del d64, cell64
     print(json.dumps(out), flush=True)
 
 

@@ -125,10 +125,13 @@ gw_status gw_tau2omega(const gw_cell* cell, const void* T, int n_omega, const vo
 gw_status gw_drain(const gw_cell* cell, const void* T, int n_omega, const void* in,
                    gw_dtype in_type, void* out, gw_dtype out_type, int basis, void* stream);
 
-/* Electron count for the chemical-potential update (Sec. 4):
- *   n = -g sum_a Re G^{R=0}_aa(beta^-)   (the last tau point),
- * written as one FP64 value to the DEVICE pointer n_dev.  GR in gr_type storage. */
-gw_status gw_density(const gw_cell* cell, const void* GR, gw_dtype gr_type, double spin_factor,
+/* Electron count for the chemical-potential update (Sec. 4), one FP64 value written
+ * to the DEVICE pointer n_dev:
+ *   space = 0: G is G^R(tau), n = -g sum_a Re G^{R=0}_aa(beta^-)   (last tau, R = 0);
+ *   space = 1: G is G(k, tau), n = -(g / N_k) sum_k sum_a Re G_aa(k, beta^-)
+ *              (the same number: G^{R=0} is the k average).
+ * G: [n_tau][N_R][N_orb][N_orb] in g_type storage; FP64 summation. */
+gw_status gw_density(const gw_cell* cell, const void* G, gw_dtype g_type, int space, double spin_factor,
                      double* n_dev, void* stream);
 
 /* Host helper: the FP64 matrix T[n_omega][n_tau] (complex, interleaved) that integrates

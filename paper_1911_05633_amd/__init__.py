@@ -37,7 +37,7 @@ SIGNATURES = {
     "gw_self_energy": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_tau2omega": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
     "gw_drain": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
-    "gw_density": (_c_int, [_vp, _vp, _c_int, _c_double, _vp, _vp]),
+    "gw_density": (_c_int, [_vp, _vp, _c_int, _c_int, _c_double, _vp, _vp]),
     "gw_tau2omega_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
     "gw_status_string": (ctypes.c_char_p, [_c_int]),
     "gw_last_error": (ctypes.c_char_p, []),
@@ -206,12 +206,13 @@ def gw_drain(cell, T, inp, out, basis=1):
                         _dtype_code(out), basis, _stream()), "gw_drain")
 
 
-def gw_density(cell, GR, spin_factor, n_out):
+def gw_density(cell, G, spin_factor, n_out, space=0):
+    """space 0: G is G^R(tau); space 1: G is G(k, tau)."""
     torch = _torch()
     if n_out.dtype != torch.float64 or n_out.numel() != 1:
         raise ValueError("n_out must be a one-element float64 device tensor")
-    _check(lib.gw_density(cell.handle, _ptr(GR, cell.elems(0), "GR"), _dtype_code(GR), float(spin_factor),
-                          _ptr(n_out, 1, "n_out"), _stream()), "gw_density")
+    _check(lib.gw_density(cell.handle, _ptr(G, cell.elems(0), "G"), _dtype_code(G), int(space),
+                          float(spin_factor), _ptr(n_out, 1, "n_out"), _stream()), "gw_density")
 
 
 def gw_tau2omega_matrix(tau, omega):

@@ -310,13 +310,15 @@ gw_status gw_self_energy(const gw_cell* c, const void* GR, const void* WR, void*
   return launch_self_energy(c, GR, WR, S, prec, (hipStream_t)stream);
 }
 
-gw_status gw_density(const gw_cell* c, const void* GR, gw_dtype t, double g, double* n_dev, void* stream) {
+gw_status gw_density(const gw_cell* c, const void* G, gw_dtype t, int space, double g, double* n_dev,
+                     void* stream) {
   gw_status st = check_cell(c);
   if (st != GW_OK) return st;
-  if (!GR || !n_dev) return fail(GW_ERR_ARG, "NULL pointer");
+  if (!G || !n_dev) return fail(GW_ERR_ARG, "NULL pointer");
   if (!valid_dtype(t)) return fail(GW_ERR_ARG, "bad dtype");
+  if (space != 0 && space != 1) return fail(GW_ERR_ARG, "space must be 0 (R) or 1 (k)");
   if (!std::isfinite(g)) return fail(GW_ERR_ARG, "spin factor must be finite");
-  return launch_density(c, GR, t, g, n_dev, (hipStream_t)stream);
+  return launch_density(c, G, t, space, g, n_dev, (hipStream_t)stream);
 }
 
 // T[m][j] for exact integration of the piecewise-linear interpolant against exp(i w tau).

@@ -234,22 +234,20 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
         return a1;
       };
       typename M::acc acc1 = gemm1(0);
+#pragma unroll 1
+      for (int tt = 0; tt < nTB; ++tt) {
+        typename M::acc nxt = {0, 0, 0, 0};
+        if (tt + 1 < nTB) nxt = gemm1(tt + 1);
 #pragma unroll
-      for (int tt = 0; tt < kTB; ++tt) {
-        if (tt < nTB) {
-          typename M::acc nxt = {0, 0, 0, 0};
-          if (tt + 1 < nTB) nxt = gemm1(tt + 1);
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int Jt = 0; Jt < kJT; ++Jt)
-              if (Jt < nJT) {
-                const RT a = Cb[(16 * Jt + li) * kCS + 8 * tt + 4 * h + lk];
-                acc2[Jt][0] = M::op(a, acc1[2 * h], acc2[Jt][0]);
-                acc2[Jt][1] = M::op(a, acc1[2 * h + 1], acc2[Jt][1]);
-              }
-          acc1 = nxt;
-        }
+          for (int Jt = 0; Jt < kJT; ++Jt)
+            if (Jt < nJT) {
+              const RT a = Cb[(16 * Jt + li) * kCS + 8 * tt + 4 * h + lk];
+              acc2[Jt][0] = M::op(a, acc1[2 * h], acc2[Jt][0]);
+              acc2[Jt][1] = M::op(a, acc1[2 * h + 1], acc2[Jt][1]);
+            }
+        acc1 = nxt;
       }
       const int I = 16 * it + li;
       if (I < q.mA) {
@@ -273,32 +271,31 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
 // ---------------------------------------------------------------------------
 // self-energy.  192 threads: wavefront w owns the 16 pairs p' = 16 w .. 16 w + 15 of
 // atom B (idle in the matrix phase if 16 w >= np_pad(B)).  W^R(tau)[A, B] streams
-// through a double-buffered LDS tile of 16 rows (I) with coalesced loads; the next
-// tile is fetched into registers while the current one is multiplied.  The
-// first product runs separately on Re W and Im W (rows I), so every 16-byte W
-// element read from LDS feeds two MFMAs.
+// through an LDS tile of 16 rows (I) with coalesced loads; the next tile is
+// fetched into registers while the current one is multiplied.  The first product
+// runs separately on Re W and Im W (rows I), so every 16-byte W element read from
+// LDS feeds two MFMAs.  The W tile and the K block share one LDS region, which
+// keeps a workgroup under 40 KB so that four of them (three wavefronts per SIMD)
+// fit on a compute unit.
 // ---------------------------------------------------------------------------
 constexpr int kWS = kMP + 1;                     // W tile row stride (complex)
 constexpr int kKS = kPL + 1;                     // K row stride (complex)
-constexpr int kUnf = 9 * 9 * 9;                  // (a, a', b) partial sums for n <= 9
 constexpr int kSThreads = 192;
 constexpr int kWPT = (16 * kMP + kSThreads - 1) / kSThreads;
 
 template <class RT, class CT>
-__global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, const CT* __restrict__ WR,
+__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_mfma(const CT* __restrict__ GR, const CT* __restrict__ WR,
                                                  double2* __restrict__ S, const RT* __restrict__ CpA,
                                                  const RT* __restrict__ CpB, const PairArgs q) {
   using M = Mma<RT>;
   typedef typename M::cplx CR;
-  constexpr size_t kWbytes = 2 * 16 * kWS * sizeof(CR);
-  constexpr size_t kKbytes = kPL * kKS * sizeof(CR) + kUnf * sizeof(double2);
+  constexpr size_t kWbytes = 16 * kWS * sizeof(CR);
+  constexpr size_t kKbytes = kPL * kKS * sizeof(CR);
   __shared__ __align__(16) unsigned char U[kWbytes > kKbytes ? kWbytes : kKbytes];
   __shared__ CR Xs[81];
-  __shared__ RT Ca[kMP * kPL];
   __shared__ unsigned char pidA[81], pidB[81];
   CR* Wb = reinterpret_cast<CR*>(U);
   CR* Ks = reinterpret_cast<CR*>(U);
-  double2* Pp = reinterpret_cast<double2*>(U + kPL * kKS * sizeof(CR));
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int nIT = q.mpA / 16, nKJ = q.mpB / 4, nMT = q.nppA / 16;
   const bool mm = 16 * w < q.nppB;  // this wavefront has pairs of B
@@ -307,8 +304,10 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
   RT b1[kKJ];
 #pragma unroll
   for (int ks = 0; ks < kKJ; ++ks) b1[ks] = (mm && ks < nKJ) ? CpB[(4 * ks + lk) * q.nppB + 16 * w + li] : RT(0);
-  for (int i = tid; i < q.mpA * q.nppA; i += kSThreads) Ca[i] = CpA[i];
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+  // unfold: thread (o, half) sums a' over one half of atom A's orbitals
+  const int half_a = (q.nA + 1) / 2;
+  const int uo = tid >> 1, uh = tid & 1;
 
   struct Blk {
     int t, R, A, B;
@@ -326,6 +325,7 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
     return o;
   };
   CR wreg[kWPT];
+  CR xr;
   auto fetch = [&](const Blk& k, int it) {
     const CT* Wt = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)q.pb_off[k.A] * q.Np + q.pb_off[k.B];
 #pragma unroll
@@ -336,15 +336,6 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
       wreg[u] = mk<RT>(re, im);
     }
   };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < kWPT; ++u) {
-      const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP;
-      if (r < 16) Wb[(buf * 16 + r) * kWS + c] = wreg[u];
-    }
-  };
-
-  CR xr;
   auto fetch_x = [&](const Blk& k) {
     double re = 0, im = 0;
     if (tid < q.nA * q.nB) {
@@ -354,6 +345,14 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
     }
     xr = mk<RT>(re, im);
   };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < kWPT; ++u) {
+      const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP;
+      if (r < 16) Wb[r * kWS + c] = wreg[u];
+    }
+  };
+
   if (blockIdx.x < q.nblocks) {
     fetch(decode(blockIdx.x), 0);
     fetch_x(decode(blockIdx.x));
@@ -362,7 +361,7 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
     const Blk k = decode(blk);
     const int oA = q.orb_off[k.A], oB = q.orb_off[k.B];
     if (tid < q.nA * q.nB) Xs[tid] = xr;
-    stash(0);
+    stash();
     __syncthreads();
     typename M::acc acc2[3][2];
 #pragma unroll
@@ -370,12 +369,11 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
     for (int it = 0; it < nIT; ++it) {
       if (it + 1 < nIT) fetch(k, it + 1);
       if (mm) {
-        const CR* Wt = Wb + (it & 1) * 16 * kWS;
         typename M::acc zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < kKJ; ++ks)
           if (ks < nKJ) {
-            const CR wv = Wt[li * kWS + 4 * ks + lk];
+            const CR wv = Wb[li * kWS + 4 * ks + lk];
             zr = M::op(wv.x, b1[ks], zr);
             zi = M::op(wv.y, b1[ks], zi);
           }
@@ -386,14 +384,17 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
 #pragma unroll
           for (int m = 0; m < 3; ++m)
             if (m < nMT) {
-              const RT a = Ca[Ik * q.nppA + 16 * m + li];
+              const RT a = CpA[Ik * q.nppA + 16 * m + li];
               acc2[m][0] = M::op(a, zr[j], acc2[m][0]);
               acc2[m][1] = M::op(a, zi[j], acc2[m][1]);
             }
         }
       }
-      if (it + 1 < nIT) stash((it + 1) & 1);
       __syncthreads();
+      if (it + 1 < nIT) {
+        stash();
+        __syncthreads();
+      }
     }
     if (blk + gridDim.x < q.nblocks) {
       const Blk kn = decode(blk + gridDim.x);
@@ -409,28 +410,29 @@ __global__ __launch_bounds__(192, 2) void s_mfma(const CT* __restrict__ GR, cons
             Ks[(16 * m + M::drow(lk, j)) * kKS + 16 * w + li] = mk<RT>((double)acc2[m][0][j], (double)acc2[m][1][j]);
     }
     __syncthreads();
-    // partial sums over b' for every (a, a', b), in FP64
-    for (int i = tid; i < q.nA * q.nA * q.nB; i += kSThreads) {
-      const int ap = i / (q.nA * q.nB), r = i - ap * q.nA * q.nB, a = r / q.nB, bb = r - a * q.nB;
-      const CR* Kr = Ks + pidA[a * q.nA + ap] * kKS;
+    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'} in FP64; the two halves of the
+    // a' range sit in neighbouring lanes and are combined with one exchange
+    {
       double sr = 0, si = 0;
-      for (int bp = 0; bp < q.nB; ++bp) {
-        const CR kv = Kr[pidB[bb * q.nB + bp]], x = Xs[ap * q.nB + bp];
-        sr += (double)kv.x * x.x - (double)kv.y * x.y;
-        si += (double)kv.x * x.y + (double)kv.y * x.x;
+      const bool live = uo < q.nA * q.nB;
+      if (live) {
+        const int a = uo / q.nB, bb = uo - a * q.nB;
+        const int a0 = uh ? half_a : 0, a1 = uh ? q.nA : half_a;
+        for (int ap = a0; ap < a1; ++ap) {
+          const CR* Kr = Ks + pidA[a * q.nA + ap] * kKS;
+          for (int bp = 0; bp < q.nB; ++bp) {
+            const CR kv = Kr[pidB[bb * q.nB + bp]], x = Xs[ap * q.nB + bp];
+            sr += (double)kv.x * x.x - (double)kv.y * x.y;
+            si += (double)kv.x * x.y + (double)kv.y * x.x;
+          }
+        }
       }
-      Pp[i] = make_double2(sr, si);
-    }
-    __syncthreads();
-    for (int o = tid; o < q.nA * q.nB; o += kSThreads) {
-      double sr = 0, si = 0;
-      for (int ap = 0; ap < q.nA; ++ap) {
-        const double2 v = Pp[ap * q.nA * q.nB + o];
-        sr += v.x;
-        si += v.y;
+      sr += __shfl_xor(sr, 1);
+      si += __shfl_xor(si, 1);
+      if (live && uh == 0) {
+        const int a = uo / q.nB, bb = uo - a * q.nB;
+        S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
       }
-      const int a = o / q.nB, bb = o - a * q.nB;
-      S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
     }
     __syncthreads();
   }

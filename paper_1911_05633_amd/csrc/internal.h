@@ -78,7 +78,7 @@ gw_status launch_polarizability(const gw_cell* c, const void* GR, void* P, doubl
                                 hipStream_t s);
 gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, void* S,
                              gw_precision p, hipStream_t s);
-gw_status launch_density(const gw_cell* c, const void* GR, gw_dtype t, double g, double* n_dev,
+gw_status launch_density(const gw_cell* c, const void* G, gw_dtype t, int space, double g, double* n_dev,
                          hipStream_t s);
 
 }  // namespace gwr

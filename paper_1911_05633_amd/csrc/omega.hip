@@ -23,14 +23,13 @@ constexpr int kDrainMaxTau = 96;
 constexpr int kDrainMaxOmega = 96;
 constexpr int kDrainCols = 64;
 
+// One 1-D pass of the R -> k sum (exp(-i 2 pi j l / L)) of length L along an axis with
+// inner stride S over O outer groups; L = 2 and 4 are written as exact butterflies.
 template <int O, int L, int S>
 __device__ __forceinline__ void dft_pass_minus(double* re, double* im) {
   if constexpr (L == 1) {
     return;
   } else {
-    double cw[L], sw[L];
-#pragma unroll
-    for (int m = 0; m < L; ++m) turn(-(double)m / (double)L, cw[m], sw[m]);
 #pragma unroll
     for (int o = 0; o < O; ++o) {
 #pragma unroll
@@ -41,21 +40,56 @@ __device__ __forceinline__ void dft_pass_minus(double* re, double* im) {
           xr[l] = re[(o * L + l) * S + i];
           xi[l] = im[(o * L + l) * S + i];
         }
+        double yr[L], yi[L];
+        if constexpr (L == 2) {
+          yr[0] = xr[0] + xr[1];
+          yi[0] = xi[0] + xi[1];
+          yr[1] = xr[0] - xr[1];
+          yi[1] = xi[0] - xi[1];
+        } else if constexpr (L == 4) {
+          // w = exp(-i pi / 2) = -i:  y1 = (x0 - x2) - i (x1 - x3),  y3 = (x0 - x2) + i (x1 - x3)
+          const double ar = xr[0] + xr[2], ai = xi[0] + xi[2], br = xr[1] + xr[3], bi = xi[1] + xi[3];
+          const double cr = xr[0] - xr[2], ci = xi[0] - xi[2], dr = xr[1] - xr[3], di = xi[1] - xi[3];
+          yr[0] = ar + br;
+          yi[0] = ai + bi;
+          yr[2] = ar - br;
+          yi[2] = ai - bi;
+          yr[1] = cr + di;
+          yi[1] = ci - dr;
+          yr[3] = cr - di;
+          yi[3] = ci + dr;
+        } else {
+          double cw[L], sw[L];
+#pragma unroll
+          for (int m = 0; m < L; ++m) turn(-(double)m / (double)L, cw[m], sw[m]);
+#pragma unroll
+          for (int j = 0; j < L; ++j) {
+            double ar = 0, ai = 0;
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+              const int m = (j * l) % L;
+              ar += cw[m] * xr[l] - sw[m] * xi[l];
+              ai += cw[m] * xi[l] + sw[m] * xr[l];
+            }
+            yr[j] = ar;
+            yi[j] = ai;
+          }
+        }
 #pragma unroll
         for (int j = 0; j < L; ++j) {
-          double ar = 0, ai = 0;
-#pragma unroll
-          for (int l = 0; l < L; ++l) {
-            const int m = (j * l) % L;
-            ar += cw[m] * xr[l] - sw[m] * xi[l];
-            ai += cw[m] * xi[l] + sw[m] * xr[l];
-          }
-          re[(o * L + j) * S + i] = ar;
-          im[(o * L + j) * S + i] = ai;
+          re[(o * L + j) * S + i] = yr[j];
+          im[(o * L + j) * S + i] = yi[j];
         }
       }
     }
   }
+}
+
+template <int N1, int N2, int N3>
+__device__ __forceinline__ void r2k_regs(double* re, double* im) {
+  dft_pass_minus<N1 * N2, N3, 1>(re, im);
+  dft_pass_minus<N1, N2, N3>(re, im);
+  dft_pass_minus<1, N1, N2 * N3>(re, im);
 }
 
 // grid: one block per CB-element chunk; 256 threads = 4 wavefronts, one 16-column tile each.
@@ -163,11 +197,14 @@ __global__ __launch_bounds__(256) void drain_mfma(const double2* __restrict__ T,
 // rounded up to 4.
 constexpr int kPF = 16;  // prefetched complex values per thread (upper bound)
 
-template <int N1, int N2, int N3, int MT, class TI, class TO>
+// REG: each thread owns whole (tau, element) columns of N_R values, so the R -> k sum
+// runs in registers between the load and the LDS store; otherwise it runs in LDS.
+template <int N1, int N2, int N3, int MT, bool REG, class TI, class TO>
 __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T, int n_omega, int n_tau,
                                                    const TI* in, TO* out, long long n2, int CB,
                                                    long long nchunks) {
   constexpr int NR = N1 * N2 * N3;
+  constexpr int PU = REG ? (NR <= kPF ? kPF / NR : 1) : kPF;  // columns per thread, or values per thread
   extern __shared__ double2 lds[];
   const int tid = threadIdx.x, nthr = blockDim.x, waves = nthr >> 6;
   const int nt4 = (n_tau + 3) & ~3, ld_t = nt4 + 1, ncp = 16 * waves;
@@ -181,54 +218,88 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
   const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int col = 16 * w + li;
   const int ksn = nt4 / 4;
-  const int items = nt4 * ncp;  // LDS slots of one chunk
-  double pr[kPF], pi[kPF];
+  const int items = nt4 * ncp;
+  double pr[REG ? PU * NR : PU], pi[REG ? PU * NR : PU];
   auto fetch = [&](long long ch) {
     const long long e0 = ch * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+    if constexpr (REG) {
 #pragma unroll
-    for (int u = 0; u < kPF; ++u) {
-      const int idx = tid + nthr * u;
-      double a = 0, b = 0;
-      if (idx < items) {
-        const int t = idx / ncp, rc = idx - t * ncp;
-        if (t < n_tau && rc < ncol) {
-          const int R = rc / CB, c = rc - R * CB;
-          if (c < cb) ldc(in + ((long long)t * NR + R) * n2 + e0 + c, a, b);
+      for (int u = 0; u < PU; ++u) {
+        const int p = tid + nthr * u, t = p / CB, c = p - t * CB;
+        const bool live = t < n_tau && c < cb;
+#pragma unroll
+        for (int R = 0; R < NR; ++R) {
+          double a = 0, b = 0;
+          if (live) ldc(in + ((long long)t * NR + R) * n2 + e0 + c, a, b);
+          pr[u * NR + R] = a;
+          pi[u * NR + R] = b;
         }
       }
-      pr[u] = a;
-      pi[u] = b;
+    } else {
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int idx = tid + nthr * u;
+        double a = 0, b = 0;
+        if (idx < items) {
+          const int t = idx / ncp, rc = idx - t * ncp;
+          if (t < n_tau && rc < ncol) {
+            const int R = rc / CB, c = rc - R * CB;
+            if (c < cb) ldc(in + ((long long)t * NR + R) * n2 + e0 + c, a, b);
+          }
+        }
+        pr[u] = a;
+        pi[u] = b;
+      }
     }
   };
+  // zero the padding rows / columns of y once (never written below)
+  for (int idx = tid; idx < items; idx += nthr) {
+    const int t = idx / ncp, rc = idx - t * ncp;
+    if (t >= n_tau || rc >= ncol) y[idx] = make_double2(0.0, 0.0);
+  }
   if (blockIdx.x < nchunks) fetch(blockIdx.x);
   for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     const long long e0 = ch * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
     __syncthreads();  // T staged / previous chunk's matrix phase done with y
+    if constexpr (REG) {
 #pragma unroll
-    for (int u = 0; u < kPF; ++u) {
-      const int idx = tid + nthr * u;
-      if (idx < items) y[idx] = make_double2(pr[u], pi[u]);
-    }
-    __syncthreads();
-    if constexpr (NR > 1) {
-      for (int idx = tid; idx < n_tau * CB; idx += nthr) {
-        const int t = idx / CB, c = idx - t * CB;
-        double re[NR], im[NR];
+      for (int u = 0; u < PU; ++u) {
+        const int p = tid + nthr * u, t = p / CB, c = p - t * CB;
+        if (t < n_tau) {
+          r2k_regs<N1, N2, N3>(pr + u * NR, pi + u * NR);
 #pragma unroll
-        for (int R = 0; R < NR; ++R) {
-          const double2 v = y[t * ncp + R * CB + c];
-          re[R] = v.x;
-          im[R] = v.y;
+          for (int q = 0; q < NR; ++q) y[t * ncp + q * CB + c] = make_double2(pr[u * NR + q], pi[u * NR + q]);
         }
-        dft_pass_minus<N1 * N2, N3, 1>(re, im);
-        dft_pass_minus<N1, N2, N3>(re, im);
-        dft_pass_minus<1, N1, N2 * N3>(re, im);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) y[t * ncp + q * CB + c] = make_double2(re[q], im[q]);
       }
       __syncthreads();
+    } else {
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int idx = tid + nthr * u;
+        if (idx < items) {
+          const int t = idx / ncp, rc = idx - t * ncp;
+          if (t < n_tau && rc < ncol) y[idx] = make_double2(pr[u], pi[u]);
+        }
+      }
+      __syncthreads();
+      if constexpr (NR > 1) {
+        for (int idx = tid; idx < n_tau * CB; idx += nthr) {
+          const int t = idx / CB, c = idx - t * CB;
+          double re[NR], im[NR];
+#pragma unroll
+          for (int R = 0; R < NR; ++R) {
+            const double2 v = y[t * ncp + R * CB + c];
+            re[R] = v.x;
+            im[R] = v.y;
+          }
+          r2k_regs<N1, N2, N3>(re, im);
+#pragma unroll
+          for (int q = 0; q < NR; ++q) y[t * ncp + q * CB + c] = make_double2(re[q], im[q]);
+        }
+        __syncthreads();
+      }
     }
     if (ch + gridDim.x < nchunks) fetch(ch + gridDim.x);  // in flight during the matrix phase
     d4 t1[MT], t2[MT], t3[MT];
@@ -293,13 +364,23 @@ __global__ __launch_bounds__(256) void tau2omega_valu(const double2* __restrict_
 template <int N1, int N2, int N3, int MT, class TI, class TO>
 void run_drain_3m(const double2* T, int n_omega, int n_tau, const TI* in, TO* out, long long n2, size_t lds,
                   int waves, int CB, hipStream_t s) {
+  constexpr int NR = N1 * N2 * N3;
   const long long nchunks = (n2 + CB - 1) / CB;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)drain_3m<N1, N2, N3, MT, TI, TO>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const long long grid = nchunks < 256 ? nchunks : 256;
-  hipLaunchKernelGGL((drain_3m<N1, N2, N3, MT, TI, TO>), dim3((unsigned)grid), dim3(64 * waves), lds, s, T,
-                     n_omega, n_tau, in, out, n2, CB, nchunks);
+  const bool reg = NR <= kPF && (long long)n_tau * CB <= (long long)(kPF / NR) * 64 * waves;
+  if (NR <= kPF && reg) {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)drain_3m<N1, N2, N3, MT, true, TI, TO>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((drain_3m<N1, N2, N3, MT, true, TI, TO>), dim3((unsigned)grid), dim3(64 * waves), lds, s,
+                       T, n_omega, n_tau, in, out, n2, CB, nchunks);
+  } else {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)drain_3m<N1, N2, N3, MT, false, TI, TO>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((drain_3m<N1, N2, N3, MT, false, TI, TO>), dim3((unsigned)grid), dim3(64 * waves), lds,
+                       s, T, n_omega, n_tau, in, out, n2, CB, nchunks);
+  }
 }
 
 template <int N1, int N2, int N3, class TI, class TO>

@@ -36,7 +36,7 @@ def test_validation_without_device():
     assert lib.gw_self_energy(None, None, None, None, 0, None) == g.GW_ERR_ARG
     assert lib.gw_fourier_k2r(None, None, 0, None, 0, 0, None) == g.GW_ERR_ARG
     assert lib.gw_drain(None, None, 48, None, 0, None, 0, 1, None) == g.GW_ERR_ARG
-    assert lib.gw_density(None, None, 0, 2.0, None, None) == g.GW_ERR_ARG
+    assert lib.gw_density(None, None, 0, 0, 2.0, None, None) == g.GW_ERR_ARG
     h = ctypes.c_void_p()
     sp = np.zeros(2, dtype=np.int32)
     no = np.array([4], dtype=np.int32)

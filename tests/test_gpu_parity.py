@@ -189,6 +189,9 @@ def test_density(name):
     ref = oracle.electron_count(d["GR"][-1, 0], spec.spin)
     assert abs(float(host(n)[0]) - ref) < 1e-12 * abs(ref)
     assert abs(ref - spec.spin * spec.N_orb / 2) < 1e-9
+    nk = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g.gw_density(cell, dev(d["Gk"]), spec.spin, nk, space=1)
+    assert abs(float(host(nk)[0]) - ref) < 1e-12 * abs(ref)
 
 
 @pytest.mark.parametrize("name", ["tiny", "two_species"])
@@ -246,3 +249,37 @@ def test_mfma_kernels_match_generic_kernels(name, prec, monkeypatch):
     tol = 1e-13 if prec == "fp64" else 3e-6
     assert relmax(out["mfma"][0], out["generic"][0]) < tol
     assert relmax(out["mfma"][1], out["generic"][1]) < tol
+
+
+@pytest.mark.parametrize("name", ["tiny", "two_species", "two_species_odd"])
+def test_chained_path_mixed(name):
+    """Mixed path: complex64 G, W, P with FP32-MFMA contractions, FP64 lattice / Matsubara
+    transforms and FP64 Sigma sums, against the k-space FP64 oracle (bar: 1e-5 relative)."""
+    import torch
+    import paper_1911_05633_amd as g
+    d = case(name)
+    spec = d["spec"]
+    print(f"[chain mixed] {name}", flush=True)
+    cell = gpu_cell(d)
+    Gk = dev(d["Gk"])
+    GR = torch.empty(Gk.shape, dtype=torch.complex64, device="cuda")
+    g.gw_fourier_k2r(cell, Gk, GR, basis=0)
+    P = torch.empty((spec.n_tau, spec.N_R, spec.N_pb, spec.N_pb), dtype=torch.complex64, device="cuda")
+    g.gw_polarizability(cell, GR, P, spec.spin, prec="fp32")
+    S = torch.empty((spec.n_tau, spec.N_R, spec.N_orb, spec.N_orb), dtype=torch.complex128, device="cuda")
+    g.gw_self_energy(cell, GR, dev(d["WR"]).to(torch.complex64), S, prec="fp32")
+    tau = sc.tau_grid(spec)
+    nu = g.matsubara(spec.n_tau, spec.beta, "bosonic")
+    wf = g.matsubara(spec.n_tau, spec.beta, "fermionic")
+    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, nu)), P, P, basis=1)
+    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, wf)), S, S, basis=0)
+    n = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g.gw_density(cell, Gk, spec.spin, n, space=1)
+    Pq = oracle.polarizability_q(d["Gk"], spec, d["C"], spec.spin)
+    Sk = oracle.self_energy_k(d["Gk"], d["WR"], spec, d["C"])
+    Pw = oracle.apply_tau_to_omega(oracle.filon_matrix(tau, oracle.bosonic_frequencies(spec.n_tau, spec.beta)), Pq)
+    Sw = oracle.apply_tau_to_omega(oracle.filon_matrix(tau, oracle.fermionic_frequencies(spec.n_tau, spec.beta)), Sk)
+    eP, eS = relmax(host(P), Pw), relmax(host(S), Sw)
+    print(f"mixed-path error: P {eP:.2e}, Sigma {eS:.2e}", flush=True)
+    assert eP < 1e-5 and eS < 1e-5
+    assert abs(float(host(n)[0]) - oracle.electron_count(d["GR"][-1, 0], spec.spin)) < 1e-10

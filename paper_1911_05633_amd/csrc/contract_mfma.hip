@@ -156,26 +156,30 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   };
   // the X and Y tiles of the next block are loaded into registers (one element per thread,
   // n_A n_B <= 81 < 256) while the current block is on the matrix cores
-  CR xr, yr;
+  CT xr, yr;  // kept in the storage type until stored to LDS (no wait at the load)
+  const bool xok = tid < q.nA * q.nB;
   auto fetch = [&](const Blk& k) {
-    const int tid2 = tid;
-    double re = 0, im = 0;
-    if (tid2 < q.nA * q.nB) {
-      const int a = tid2 / q.nB, c = tid2 - a * q.nB;
-      ldc(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
-          re, im);
-    }
-    xr = mk<RT>(re, im);
-    re = im = 0;
-    if (tid2 < q.nA * q.nB) {
-      const int d = tid2 / q.nA, bb = tid2 - d * q.nA;
-      ldc(GR + ((long long)(q.n_tau - 1 - k.t) * q.NR + q.minusR[k.R]) * sl +
-              (long long)(q.orb_off[k.B] + d) * q.No + q.orb_off[k.A] + bb,
-          re, im);
-    }
-    yr = mk<RT>(re, im);
+    const int a = tid / q.nB, c = tid - a * q.nB;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
+               GR, xok);
+    const int d = tid / q.nA, bb = tid - d * q.nA;
+    yr = ldraw(GR + ((long long)(q.n_tau - 1 - k.t) * q.NR + q.minusR[k.R]) * sl +
+                   (long long)(q.orb_off[k.B] + d) * q.No + q.orb_off[k.A] + bb,
+               GR, xok);
   };
-  if (blockIdx.x < q.nblocks) fetch(decode(blockIdx.x));
+  auto stage = [&]() {
+    if (tid < q.nA * q.nB) {
+      Xs[tid] = mk<RT>((double)xr.x, (double)xr.y);
+      Ys[tid] = mk<RT>((double)yr.x, (double)yr.y);
+    }
+  };
+  // Order per block: issue the next block's G loads; form Q from this block's tiles;
+  // barrier; stage the next tiles into LDS (loads issued a Q formation earlier, before
+  // any of this block's stores); matrix phase and stores; barrier.
+  if (blockIdx.x < q.nblocks) {
+    fetch(decode(blockIdx.x));
+    stage();
+  }
   __syncthreads();
 
   for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
@@ -183,12 +187,8 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
     const int t = k.t, R = k.R;
     const int tm = q.n_tau - 1 - t, mR = q.minusR[R];
     const int pA = q.pb_off[k.A], pB = q.pb_off[k.B];
-    if (tid < q.nA * q.nB) {
-      Xs[tid] = xr;
-      Ys[tid] = yr;
-    }
-    __syncthreads();
-    if (blk + gridDim.x < q.nblocks) fetch(decode(blk + gridDim.x));
+    const bool more = blk + gridDim.x < q.nblocks;
+    if (more) fetch(decode(blk + gridDim.x));
     // Q over unordered pairs (zero outside the live pairs)
     for (int i = tid; i < q.nppA * q.nppB; i += 256) {
       const int p = i / q.nppB, pp = i - p * q.nppB;
@@ -214,6 +214,7 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
       Qs[p * kQS + pp] = mk<RT>(qr, qi);
     }
     __syncthreads();
+    if (more) stage();
 
     CT* Pd = P + ((long long)t * q.NR + R) * slp;
     CT* Pm = P + ((long long)tm * q.NR + mR) * slp;
@@ -324,45 +325,50 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     o.B = q.atomsB[iB];
     return o;
   };
-  CR wreg[kWPT];
-  CR xr;
+  CT wreg[kWPT];  // prefetched W tile and X element, in the storage type
+  CT xr;
+  int wtile = 0;  // I tile of the W values in wreg (their validity is applied at stash())
   auto fetch = [&](const Blk& k, int it) {
     const CT* Wt = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)q.pb_off[k.A] * q.Np + q.pb_off[k.B];
 #pragma unroll
     for (int u = 0; u < kWPT; ++u) {
       const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP, I = 16 * it + r;
-      double re = 0, im = 0;
-      if (r < 16 && I < q.mA && c < q.mB) ldc(Wt + (long long)I * q.Np + c, re, im);
-      wreg[u] = mk<RT>(re, im);
+      const bool ok = r < 16 && I < q.mA && c < q.mB;
+      wreg[u] = ldraw(Wt + (long long)I * q.Np + c, WR, ok);
     }
+    wtile = it;
   };
+  const bool xok = tid < q.nA * q.nB;
   auto fetch_x = [&](const Blk& k) {
-    double re = 0, im = 0;
-    if (tid < q.nA * q.nB) {
-      const int a = tid / q.nB, c = tid - a * q.nB;
-      ldc(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
-          re, im);
-    }
-    xr = mk<RT>(re, im);
+    const int a = tid / q.nB, c = tid - a * q.nB;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
+               GR, xok);
   };
   auto stash = [&]() {
 #pragma unroll
     for (int u = 0; u < kWPT; ++u) {
-      const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP;
-      if (r < 16) Wb[r * kWS + c] = wreg[u];
+      const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP, I = 16 * wtile + r;
+      if (r < 16) {
+        const CT v = keep(wreg[u], I < q.mA && c < q.mB);
+        Wb[r * kWS + c] = mk<RT>((double)v.x, (double)v.y);
+      }
     }
   };
 
+  // The first W tile and the X tile of the next block are staged after the unfold has
+  // finished with K (same LDS) and before this block's Sigma stores, so waiting for
+  // those loads never waits for fresh stores.
   if (blockIdx.x < q.nblocks) {
     fetch(decode(blockIdx.x), 0);
     fetch_x(decode(blockIdx.x));
+    if (tid < q.nA * q.nB) Xs[tid] = mk<RT>((double)xr.x, (double)xr.y);
+    stash();
   }
+  __syncthreads();
   for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
     const Blk k = decode(blk);
     const int oA = q.orb_off[k.A], oB = q.orb_off[k.B];
-    if (tid < q.nA * q.nB) Xs[tid] = xr;
-    stash();
-    __syncthreads();
+    const bool more = blk + gridDim.x < q.nblocks;
     typename M::acc acc2[3][2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = typename M::acc{0, 0, 0, 0};
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
         __syncthreads();
       }
     }
-    if (blk + gridDim.x < q.nblocks) {
+    if (more) {
       const Blk kn = decode(blk + gridDim.x);
       fetch(kn, 0);
       fetch_x(kn);
@@ -429,6 +435,11 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       }
       sr += __shfl_xor(sr, 1);
       si += __shfl_xor(si, 1);
+      __syncthreads();  // K and X no longer read
+      if (more) {
+        if (tid < q.nA * q.nB) Xs[tid] = mk<RT>((double)xr.x, (double)xr.y);
+        stash();
+      }
       if (live && uh == 0) {
         const int a = uo / q.nB, bb = uo - a * q.nB;
         S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);

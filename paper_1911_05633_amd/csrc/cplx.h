@@ -23,3 +23,24 @@ __device__ __forceinline__ void stc(float2* p, double re, double im) {
 __device__ __forceinline__ void turn(double frac, double& c, double& s) { sincospi(2.0 * frac, &s, &c); }
 
 }  // namespace gwr
+
+namespace gwr {
+
+// Prefetch helpers.  A prefetch loads unconditionally (from `p` when ok, else from the
+// always-valid `base`) and keeps the value in its storage type; the validity mask is
+// applied only when the value is consumed (keep()).  Neither a conversion nor a zero
+// fill touches the destination register at the load, so the compiler never has to wait
+// for the load (or, memory counters completing in order, for older stores) there.
+template <class T>
+__device__ __forceinline__ T ldraw(const T* p, const T* base, bool ok) {
+  return *(ok ? p : base);
+}
+template <class T>
+__device__ __forceinline__ T keep(const T& v, bool ok) {
+  T z;
+  z.x = ok ? v.x : 0;
+  z.y = ok ? v.y : 0;
+  return z;
+}
+
+}  // namespace gwr

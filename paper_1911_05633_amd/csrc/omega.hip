@@ -219,7 +219,8 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
   const int col = 16 * w + li;
   const int ksn = nt4 / 4;
   const int items = nt4 * ncp;
-  double pr[REG ? PU * NR : PU], pi[REG ? PU * NR : PU];
+  // prefetch buffer in the storage type: no conversion (and so no wait) at the load
+  TI raw[REG ? PU * NR : PU];
   auto fetch = [&](long long ch) {
     const long long e0 = ch * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
@@ -229,27 +230,15 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
         const int p = tid + nthr * u, t = p / CB, c = p - t * CB;
         const bool live = t < n_tau && c < cb;
 #pragma unroll
-        for (int R = 0; R < NR; ++R) {
-          double a = 0, b = 0;
-          if (live) ldc(in + ((long long)t * NR + R) * n2 + e0 + c, a, b);
-          pr[u * NR + R] = a;
-          pi[u * NR + R] = b;
-        }
+        for (int R = 0; R < NR; ++R) raw[u * NR + R] = ldraw(in + ((long long)t * NR + R) * n2 + e0 + c, in, live);
       }
     } else {
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
         const int idx = tid + nthr * u;
-        double a = 0, b = 0;
-        if (idx < items) {
-          const int t = idx / ncp, rc = idx - t * ncp;
-          if (t < n_tau && rc < ncol) {
-            const int R = rc / CB, c = rc - R * CB;
-            if (c < cb) ldc(in + ((long long)t * NR + R) * n2 + e0 + c, a, b);
-          }
-        }
-        pr[u] = a;
-        pi[u] = b;
+        const int t = idx / ncp, rc = idx - t * ncp, R = rc / CB, c = rc - R * CB;
+        const bool live = idx < items && t < n_tau && rc < ncol && c < cb;
+        raw[u] = ldraw(in + ((long long)t * NR + R) * n2 + e0 + c, in, live);
       }
     }
   };
@@ -258,33 +247,42 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
     const int t = idx / ncp, rc = idx - t * ncp;
     if (t >= n_tau || rc >= ncol) y[idx] = make_double2(0.0, 0.0);
   }
-  if (blockIdx.x < nchunks) fetch(blockIdx.x);
-  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+  // fill y from the prefetch registers (R -> k in registers, or in LDS)
+  auto fill = [&](long long ch) {
     const long long e0 = ch * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
-    __syncthreads();  // T staged / previous chunk's matrix phase done with y
     if constexpr (REG) {
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
         const int p = tid + nthr * u, t = p / CB, c = p - t * CB;
         if (t < n_tau) {
-          r2k_regs<N1, N2, N3>(pr + u * NR, pi + u * NR);
+          const bool live = c < cb;
+          double pr[NR], pi[NR];
 #pragma unroll
-          for (int q = 0; q < NR; ++q) y[t * ncp + q * CB + c] = make_double2(pr[u * NR + q], pi[u * NR + q]);
+          for (int R = 0; R < NR; ++R) {
+            const TI v = keep(raw[u * NR + R], live);
+            pr[R] = (double)v.x;
+            pi[R] = (double)v.y;
+          }
+          r2k_regs<N1, N2, N3>(pr, pi);
+#pragma unroll
+          for (int q = 0; q < NR; ++q) y[t * ncp + q * CB + c] = make_double2(pr[q], pi[q]);
         }
       }
-      __syncthreads();
     } else {
 #pragma unroll
       for (int u = 0; u < PU; ++u) {
         const int idx = tid + nthr * u;
         if (idx < items) {
           const int t = idx / ncp, rc = idx - t * ncp;
-          if (t < n_tau && rc < ncol) y[idx] = make_double2(pr[u], pi[u]);
+          if (t < n_tau && rc < ncol) {
+            const TI v = keep(raw[u], rc - (rc / CB) * CB < cb);
+            y[idx] = make_double2((double)v.x, (double)v.y);
+          }
         }
       }
-      __syncthreads();
       if constexpr (NR > 1) {
+        __syncthreads();
         for (int idx = tid; idx < n_tau * CB; idx += nthr) {
           const int t = idx / CB, c = idx - t * CB;
           double re[NR], im[NR];
@@ -298,10 +296,22 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
 #pragma unroll
           for (int q = 0; q < NR; ++q) y[t * ncp + q * CB + c] = make_double2(re[q], im[q]);
         }
-        __syncthreads();
       }
     }
-    if (ch + gridDim.x < nchunks) fetch(ch + gridDim.x);  // in flight during the matrix phase
+  };
+  // Order per chunk: matrix phase on y; barrier; y <- next chunk (its loads were issued a
+  // whole matrix phase earlier); store this chunk's results; issue the loads of the chunk
+  // after next; barrier.  Waiting for the prefetched data never waits for fresh stores.
+  if (blockIdx.x < nchunks) {
+    fetch(blockIdx.x);
+    __syncthreads();  // T and the zero padding staged
+    fill(blockIdx.x);
+    if (blockIdx.x + gridDim.x < nchunks) fetch(blockIdx.x + gridDim.x);
+    __syncthreads();
+  }
+  for (long long ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const long long e0 = ch * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
     d4 t1[MT], t2[MT], t3[MT];
 #pragma unroll
     for (int i = 0; i < MT; ++i) t1[i] = t2[i] = t3[i] = d4{0, 0, 0, 0};
@@ -317,6 +327,9 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
         t3[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.x + tv.y, ys, t3[i], 0, 0, 0);
       }
     }
+    __syncthreads();  // every wavefront is done reading y
+    const long long nxt = ch + gridDim.x;
+    if (nxt < nchunks) fill(nxt);
     // D fragment: register j of lane group lk is frequency 16 i + lk + 4 j, column `col`
     if (col < ncol) {
       const int q = col / CB, c = col - q * CB;
@@ -331,6 +344,152 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
           }
       }
     }
+    if (nxt + gridDim.x < nchunks) fetch(nxt + gridDim.x);
+    __syncthreads();
+  }
+}
+
+// Ping-pong variant: two streams of four wavefronts share T in LDS and own one y
+// buffer each (64 columns).  Between two barriers one stream runs its matrix phase
+// while the other stores its previous results, refills its y from the prefetch
+// registers and issues the loads of its chunk after next, so HBM traffic and MFMA
+// overlap inside one workgroup.  Stream s handles chunks 2 blockIdx + s + 2 k gridDim.
+template <int N1, int N2, int N3, int MT, class TI, class TO>
+__global__ __launch_bounds__(512, 1) void drain_pp(const double2* __restrict__ T, int n_omega, int n_tau,
+                                                   const TI* in, TO* out, long long n2, int CB,
+                                                   long long nchunks) {
+  constexpr int NR = N1 * N2 * N3;
+  constexpr int NCP = 64;                              // columns per stream chunk
+  constexpr int PU = NR <= kPF ? kPF / NR : 1;          // (tau, element) columns per thread
+  extern __shared__ double2 lds[];
+  const int tid = threadIdx.x;
+  const int nt4 = (n_tau + 7) & ~7, ld_t = nt4 + 1;  // K rounded to 8: an even number of K steps
+  double2* Ts = lds;                                   // [16 MT][ld_t]
+  const int stream = tid >> 8, stid = tid & 255;       // 256 threads per stream
+  double2* y = lds + 16 * MT * ld_t + stream * nt4 * NCP;
+  for (int i = tid; i < 16 * MT * ld_t; i += 512) {
+    const int m = i / ld_t, t = i - m * ld_t;
+    Ts[i] = (m < n_omega && t < n_tau) ? T[(long long)m * n_tau + t] : make_double2(0.0, 0.0);
+  }
+  const int ncol = NR * CB;
+  for (int idx = stid; idx < nt4 * NCP; idx += 256) {  // padding rows / columns stay zero
+    const int t = idx / NCP, rc = idx - t * NCP;
+    if (t >= n_tau || rc >= ncol) y[idx] = make_double2(0.0, 0.0);
+  }
+  const int lane = tid & 63, w = (tid >> 6) & 3, li = lane & 15, lk = lane >> 4;
+  const int col = 16 * w + li;
+  const int ksn = nt4 / 4;
+  const long long stride = 2LL * gridDim.x;
+  const long long first = 2LL * blockIdx.x + stream;
+  TI raw[PU * NR];
+  auto fetch = [&](long long ch) {
+    const long long e0 = ch * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int p = stid + 256 * u, t = p / CB, c = p - t * CB;
+      const bool live = ch < nchunks && t < n_tau && c < cb;
+#pragma unroll
+      for (int R = 0; R < NR; ++R) raw[u * NR + R] = ldraw(in + ((long long)t * NR + R) * n2 + e0 + c, in, live);
+    }
+  };
+  auto fill = [&](long long ch) {
+    const long long e0 = ch * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int p = stid + 256 * u, t = p / CB, c = p - t * CB;
+      if (t < n_tau) {
+        const bool live = c < cb;
+        double pr[NR], pi[NR];
+#pragma unroll
+        for (int R = 0; R < NR; ++R) {
+          const TI v = keep(raw[u * NR + R], live);
+          pr[R] = (double)v.x;
+          pi[R] = (double)v.y;
+        }
+        r2k_regs<N1, N2, N3>(pr, pi);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) y[t * NCP + q * CB + c] = make_double2(pr[q], pi[q]);
+      }
+    }
+  };
+  d4 t1[MT], t2[MT], t3[MT];
+  // Two named operand sets: the LDS reads of one K step are issued before the MFMAs of
+  // the other, so a single wavefront keeps its SIMD's matrix pipe busy.
+  auto matrix = [&]() {
+#pragma unroll
+    for (int i = 0; i < MT; ++i) t1[i] = t2[i] = t3[i] = d4{0, 0, 0, 0};
+    double2 ya, yb, ta[MT], tb[MT];
+    auto load = [&](int ks, double2& yv, double2* tv) {
+      const int tau = 4 * ks + lk;
+      yv = y[tau * NCP + col];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) tv[i] = Ts[(16 * i + li) * ld_t + tau];
+    };
+    auto mma = [&](const double2& yv, const double2* tv) {
+      const double ys = yv.x + yv.y;
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        t1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].x, yv.x, t1[i], 0, 0, 0);
+        t2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].y, yv.y, t2[i], 0, 0, 0);
+        t3[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].x + tv[i].y, ys, t3[i], 0, 0, 0);
+      }
+    };
+    load(0, ya, ta);
+    for (int ks = 0; ks < ksn; ks += 2) {  // ksn is even; the last read of ya is a spare one
+      load(ks + 1, yb, tb);
+      mma(ya, ta);
+      load(ks + 2 < ksn ? ks + 2 : ks, ya, ta);
+      mma(yb, tb);
+      // keep this order: reads of one set, MFMAs of the other, reads, MFMAs
+      __builtin_amdgcn_sched_group_barrier(0x100, MT + 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * MT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, MT + 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * MT, 0);
+    }
+  };
+  auto store = [&](long long ch) {
+    const long long e0 = ch * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+    if (col < ncol) {
+      const int q = col / CB, c = col - q * CB;
+      if (c < cb) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int m = 16 * i + lk + 4 * j;
+            if (m < n_omega)
+              stc(out + ((long long)m * NR + q) * n2 + e0 + c, t1[i][j] - t2[i][j], t3[i][j] - t1[i][j] - t2[i][j]);
+          }
+      }
+    }
+  };
+  // prologue: y <- chunk 0 of each stream, prefetch registers <- chunk 1
+  fetch(first);
+  __syncthreads();
+  if (first < nchunks) fill(first);
+  fetch(first + stride);
+  __syncthreads();
+  // half step h: stream h % 2 multiplies its chunk k = h / 2; the other stream stores
+  // its chunk k' = (h - 1) / 2, refills y with k' + 1 and prefetches k' + 2
+  const long long kmax = (nchunks - first + stride - 1) / stride;  // chunks of this stream
+  const long long kmax0 = (nchunks - 2LL * blockIdx.x + stride - 1) / stride;
+  const long long nhalf = 2 * kmax0 + 2;
+  for (long long h = 0; h < nhalf; ++h) {
+    if ((h & 1) == stream) {
+      const long long k = h >> 1;
+      if (k < kmax) matrix();
+    } else if (h >= 1) {
+      const long long k = (h - 1) >> 1;
+      if (k < kmax) {
+        store(first + k * stride);
+        if (k + 1 < kmax) fill(first + (k + 1) * stride);
+        fetch(first + (k + 2) * stride);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -386,10 +545,36 @@ void run_drain_3m(const double2* T, int n_omega, int n_tau, const TI* in, TO* ou
 template <int N1, int N2, int N3, class TI, class TO>
 void run_drain(const double2* T, int n_omega, int n_tau, const TI* in, TO* out, long long n2, hipStream_t s) {
   constexpr int NR = N1 * N2 * N3;
-  // persistent 3M kernel: the widest chunk (<= 128 columns) whose T + y fit in LDS and
-  // whose prefetch fits the per-thread register budget
   const int MT = (n_omega + 15) / 16;
   const int nt4 = (n_tau + 3) & ~3;
+  // ping-pong kernel: two 64-column streams; needs whole (tau, element) columns per thread
+  {
+    const int CB = NR >= 64 ? 1 : 64 / NR;
+    const int nt8 = (n_tau + 7) & ~7;
+    const size_t lds = (size_t)(16 * MT * (nt8 + 1) + 2 * nt8 * 64) * sizeof(double2);
+    const bool regs_ok = NR <= kPF && (long long)n_tau * CB <= (long long)(kPF / (NR <= kPF ? NR : 1)) * 256;
+    if (MT <= 4 && NR * CB <= 64 && lds <= 160 * 1024 && regs_ok && NR <= kPF) {
+      const long long nchunks = (n2 + CB - 1) / CB;
+      const long long grid = (nchunks + 1) / 2 < 256 ? (nchunks + 1) / 2 : 256;
+#define GWR_PP(mt)                                                                                     \
+  case mt:                                                                                             \
+    (void)hipFuncSetAttribute((const void*)drain_pp<N1, N2, N3, mt, TI, TO>,                           \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
+    hipLaunchKernelGGL((drain_pp<N1, N2, N3, mt, TI, TO>), dim3((unsigned)grid), dim3(512), lds, s, T, \
+                       n_omega, n_tau, in, out, n2, CB, nchunks);                                      \
+    return;
+      switch (MT) {
+        GWR_PP(1)
+        GWR_PP(2)
+        GWR_PP(3)
+        GWR_PP(4)
+        default: break;
+      }
+#undef GWR_PP
+    }
+  }
+  // persistent 3M kernel: the widest chunk (<= 128 columns) whose T + y fit in LDS and
+  // whose prefetch fits the per-thread register budget
   for (int cols = 128; cols >= 16 && MT <= 4; cols /= 2) {
     const int CB = NR >= cols ? 1 : cols / NR;
     const int waves = (NR * CB + 15) / 16;

@@ -1,6 +1,7 @@
 """Benchmark of one space-time P + Sigma step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--prec fp64|fp32|bf16x3]
+    python bench.py --serve [--requests 200] [--slots 4]
 
 A step is the whole path on one synthetic cell with inputs resident in HBM:
     G(k,tau) -k2r-> G(R,tau) -> P (Eq. 5) and Sigma (Eq. 8, with W(R,tau))
@@ -86,8 +87,8 @@ def run_step(g, cell, d, spec, prec, ev=None):
         lambda: g.gw_fourier_k2r(cell, d["Gk"], d["GR"], basis=0),
         lambda: g.gw_polarizability(cell, d["GR"], d["P"], spec.spin, prec=prec),
         lambda: g.gw_self_energy(cell, d["GR"], d["W"], d["S"], prec=prec),
-        lambda: g.gw_drain(cell, d["TP"], d["P"], d["P"], basis=1),
-        lambda: g.gw_drain(cell, d["TS"], d["S"], d["S"], basis=0),
+        lambda: g.gw_drain(cell, d["TP"], d["P"], d["P"], basis=1, parity=1),
+        lambda: g.gw_drain(cell, d["TS"], d["S"], d["S"], basis=0, parity=-1),
         (lambda: g.gw_density(cell, d["GR"], spec.spin, d["n"], space=0)) if prec == "fp64" else
         (lambda: g.gw_density(cell, d["Gk"], spec.spin, d["n"], space=1)),
     ]
@@ -181,6 +182,66 @@ def time_path(g, spec, prec, steps, warmup, torch, log):
     return d, cell, wall / steps * 1e3, per
 
 
+def serve_bench(args, torch, log):
+    """Serving mix: a seeded Poisson stream of independent P + Sigma requests over 2-, 8-, 24-,
+    40- and 72-atom cells with 16-48 tau points, served by the continuous-batching loop on
+    the mixed path; compared with one-at-a-time FP64 service of the same stream."""
+    import synthcell as sc
+    from paper_1911_05633_amd import serve
+
+    def run(ex, reqs, slots):
+        t0 = time.perf_counter()
+        recs = serve.Server(ex, ex.capacity, slots=slots).run(reqs)
+        s = serve.summarize(recs)
+        s["wall_s"] = time.perf_counter() - t0
+        bad = [(r.request_id, r.status, r.error) for r in recs if r.status != "done"]
+        if bad:
+            raise RuntimeError(f"requests not served: {bad[:5]}")
+        nerr = max(abs(r.result["n"] - r.result["n_expected"]) / r.result["n_expected"] for r in recs)
+        s["max_electron_count_rel_err"] = nerr
+        return s, recs
+
+    def prepare(ex):
+        t0 = time.perf_counter()
+        for kind in sc.SERVING_KINDS:
+            for nt in sc.SERVING_NTAU:
+                ex.prepare(sc.Request(-1, 0.0, kind, nt))
+        # one request per kind on the device (kernel and allocator warm-up)
+        run(ex, [sc.Request(i, 0.0, kind, sc.SERVING_NTAU[0]) for i, kind in enumerate(sc.SERVING_KINDS)], 1)
+        log(f"serving executor ({ex.prec}) prepared in {time.perf_counter() - t0:.1f}s, pool "
+            f"{ex.capacity / 2**30:.1f} GiB")
+
+    n = args.requests
+    ex = serve.GWExecutor(prec="fp32", slots=args.slots)
+    prepare(ex)
+    burst, _ = run(ex, sc.request_stream(n, rate=1.0, burst=True), args.slots)
+    log(f"burst: {burst}")
+    rate = 0.7 * burst["throughput_req_per_s"]
+    reqs = sc.request_stream(n, rate=rate)
+    mixed, _ = run(ex, reqs, args.slots)
+    log(f"poisson at {rate:.2f} req/s (0.7 of the burst rate), mixed path: {mixed}")
+    del ex
+    torch.cuda.empty_cache()
+    ex64 = serve.GWExecutor(prec="fp64", slots=1)
+    prepare(ex64)
+    base, _ = run(ex64, reqs, 1)
+    log(f"same stream, one at a time, FP64: {base}")
+    del ex64
+    torch.cuda.empty_cache()
+    out = {
+        "metric": "serving mix: P+Sigma requests/s with p50/p99 latency (continuous batching, mixed path)",
+        "value": mixed["throughput_req_per_s"], "unit": "req/s", "n_gpus": 1, "higher_is_better": True,
+        "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{n} requests, Poisson arrivals at {rate:.3f} req/s (0.7 of the measured burst "
+                               f"rate), cells uniform over {list(sc.SERVING_KINDS)}, n_tau uniform over "
+                               f"{list(sc.SERVING_NTAU)}", "slots": args.slots},
+        "burst_capacity": burst, "poisson_mixed": mixed, "baseline_fp64_one_at_a_time": base,
+        "speedup_throughput_vs_baseline": mixed["throughput_req_per_s"] / base["throughput_req_per_s"],
+        "p99_ratio_baseline_over_mixed": base["p99_ms"] / mixed["p99_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +252,9 @@ def main():
                     help="contraction arithmetic: fp32 = the mixed path (default), fp64 = plain FP64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the step benchmark")
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -204,6 +268,9 @@ def main():
     import synthcell as sc
     import paper_1911_05633_amd as g
 
+    if args.serve:
+        serve_bench(args, torch, log)
+        return
     spec = sc.config(args.config)
     log(f"config {args.config}: {spec.name}, {spec.n_atoms} atoms, N_orb {spec.N_orb}, N_pb {spec.N_pb}, "
         f"N_R {spec.N_R}, n_tau {spec.n_tau}, prec {args.prec}")

@@ -116,13 +116,21 @@ gw_status gw_self_energy(const gw_cell* cell, const void* GR, const void* WR, vo
  *   out[m][...] = sum_i T[m][i] in[i][...],  m < n_omega,
  * with T a DEVICE complex128 matrix [n_omega][n_tau] (see gw_tau2omega_matrix).
  * The trailing shape is [N_R][n][n] with n = N_orb (basis 0) or N_pb (basis 1).
+ * parity declares the mirror symmetry of T about beta/2:
+ *    0 : none assumed (any T);
+ *   +1 : T[m][n_tau-1-i] == conj(T[m][i])   (bosonic frequencies on a symmetric grid);
+ *   -1 : T[m][n_tau-1-i] == -conj(T[m][i])  (fermionic frequencies on a symmetric grid).
+ * With parity != 0 the kernels may read only the columns i <= (n_tau-1)/2 of T and pair
+ * each tau with its mirror (two real GEMMs instead of three); the result for a T that
+ * lacks the declared symmetry is unspecified.  T must still hold all n_tau columns.
+ * parity outside {-1, 0, +1} is GW_ERR_ARG.
  * FP64 arithmetic.  in == out is allowed when in_type == out_type. */
-gw_status gw_tau2omega(const gw_cell* cell, const void* T, int n_omega, const void* in,
+gw_status gw_tau2omega(const gw_cell* cell, const void* T, int n_omega, int parity, const void* in,
                        gw_dtype in_type, void* out, gw_dtype out_type, int basis, void* stream);
 
 /* R -> k followed by tau -> Matsubara in one pass over HBM (product of the two
- * operators above; same argument rules). */
-gw_status gw_drain(const gw_cell* cell, const void* T, int n_omega, const void* in,
+ * operators above; same argument rules, parity included). */
+gw_status gw_drain(const gw_cell* cell, const void* T, int n_omega, int parity, const void* in,
                    gw_dtype in_type, void* out, gw_dtype out_type, int basis, void* stream);
 
 /* Electron count for the chemical-potential update (Sec. 4), one FP64 value written

@@ -35,8 +35,8 @@ SIGNATURES = {
     "gw_fourier_r2k": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
     "gw_polarizability": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
     "gw_self_energy": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
-    "gw_tau2omega": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
-    "gw_drain": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
+    "gw_tau2omega": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
+    "gw_drain": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
     "gw_density": (_c_int, [_vp, _vp, _c_int, _c_int, _c_double, _vp, _vp]),
     "gw_tau2omega_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
     "gw_status_string": (ctypes.c_char_p, [_c_int]),
@@ -47,6 +47,14 @@ SIGNATURES = {
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1911_05633_amd.build`")
+    # Tensors handed to the library are device pointers of torch's HIP runtime, so the
+    # library must bind to that same runtime: torch (which loads its own libamdhip64)
+    # goes first, and libgwr's libamdhip64.so.7 dependency then resolves to it instead
+    # of loading a second, separately initialised runtime from the system path.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
@@ -72,7 +80,7 @@ def _check(st, where):
 
 
 def _torch():
-    import torch  # deferred: the CPU-only tests load the library without torch
+    import torch
     return torch
 
 
@@ -190,17 +198,21 @@ def _T_ptr(cell, T):
     return _ptr(T, T.numel(), "T"), int(T.shape[0])
 
 
-def gw_tau2omega(cell, T, inp, out, basis=0):
+def gw_tau2omega(cell, T, inp, out, basis=0, parity=0):
+    """parity: 0 (general T), +1 (bosonic) or -1 (fermionic) mirror symmetry of T."""
     tp, n_omega = _T_ptr(cell, T)
-    _check(lib.gw_tau2omega(cell.handle, tp, n_omega, _ptr(inp, cell.elems(basis), "in"), _dtype_code(inp),
+    _check(lib.gw_tau2omega(cell.handle, tp, n_omega, int(parity), _ptr(inp, cell.elems(basis), "in"),
+                            _dtype_code(inp),
                             _ptr(out, cell.elems(basis, n_omega) if out.data_ptr() != inp.data_ptr()
                                  else out.numel(), "out"),
                             _dtype_code(out), basis, _stream()), "gw_tau2omega")
 
 
-def gw_drain(cell, T, inp, out, basis=1):
+def gw_drain(cell, T, inp, out, basis=1, parity=0):
+    """parity: 0 (general T), +1 (bosonic) or -1 (fermionic) mirror symmetry of T."""
     tp, n_omega = _T_ptr(cell, T)
-    _check(lib.gw_drain(cell.handle, tp, n_omega, _ptr(inp, cell.elems(basis), "in"), _dtype_code(inp),
+    _check(lib.gw_drain(cell.handle, tp, n_omega, int(parity), _ptr(inp, cell.elems(basis), "in"),
+                        _dtype_code(inp),
                         _ptr(out, cell.elems(basis, n_omega) if out.data_ptr() != inp.data_ptr()
                              else out.numel(), "out"),
                         _dtype_code(out), basis, _stream()), "gw_drain")

@@ -247,11 +247,12 @@ gw_status gw_fourier_r2k(const gw_cell* c, const void* in, gw_dtype it, void* ou
   return fourier_common(c, in, it, out, ot, basis, stream, -1);
 }
 
-static gw_status omega_common(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it,
-                              void* out, gw_dtype ot, int basis, long long* n_out) {
+static gw_status omega_common(const gw_cell* c, const void* T, int n_omega, int parity, const void* in,
+                              gw_dtype it, void* out, gw_dtype ot, int basis, long long* n_out) {
   gw_status st = check_cell(c);
   if (st != GW_OK) return st;
   if (!T || !in || !out) return fail(GW_ERR_ARG, "NULL tensor");
+  if (parity < -1 || parity > 1) return fail(GW_ERR_ARG, "parity must be -1, 0 or +1");
   if (!valid_dtype(it) || !valid_dtype(ot)) return fail(GW_ERR_ARG, "bad dtype");
   if (basis != 0 && basis != 1) return fail(GW_ERR_ARG, "basis must be 0 (orbital) or 1 (product)");
   if (n_omega < 1 || n_omega > 256) return fail(GW_ERR_SHAPE, "n_omega must be in [1, 256]");
@@ -266,20 +267,21 @@ static gw_status omega_common(const gw_cell* c, const void* T, int n_omega, cons
   return GW_OK;
 }
 
-gw_status gw_tau2omega(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it, void* out,
-                       gw_dtype ot, int basis, void* stream) {
+gw_status gw_tau2omega(const gw_cell* c, const void* T, int n_omega, int parity, const void* in, gw_dtype it,
+                       void* out, gw_dtype ot, int basis, void* stream) {
   long long n = 0;
-  gw_status st = omega_common(c, T, n_omega, in, it, out, ot, basis, &n);
+  gw_status st = omega_common(c, T, n_omega, parity, in, it, out, ot, basis, &n);
   if (st != GW_OK) return st;
-  return launch_tau2omega(c, T, n_omega, in, it, out, ot, (long long)c->N_R * n * n, (hipStream_t)stream);
+  return launch_tau2omega(c, T, n_omega, parity, in, it, out, ot, (long long)c->N_R * n * n,
+                          (hipStream_t)stream);
 }
 
-gw_status gw_drain(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it, void* out,
-                   gw_dtype ot, int basis, void* stream) {
+gw_status gw_drain(const gw_cell* c, const void* T, int n_omega, int parity, const void* in, gw_dtype it,
+                   void* out, gw_dtype ot, int basis, void* stream) {
   long long n = 0;
-  gw_status st = omega_common(c, T, n_omega, in, it, out, ot, basis, &n);
+  gw_status st = omega_common(c, T, n_omega, parity, in, it, out, ot, basis, &n);
   if (st != GW_OK) return st;
-  return launch_drain(c, T, n_omega, in, it, out, ot, (int)n, (hipStream_t)stream);
+  return launch_drain(c, T, n_omega, parity, in, it, out, ot, (int)n, (hipStream_t)stream);
 }
 
 gw_status gw_polarizability(const gw_cell* c, const void* GR, void* P, double g, gw_precision prec,

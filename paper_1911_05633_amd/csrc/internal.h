@@ -70,9 +70,9 @@ inline size_t csize(gw_dtype t) { return t == GW_C128 ? 16 : 8; }
 // launchers (defined in the kernel sources); all validation is done by the caller
 gw_status launch_fourier(const gw_cell* c, const void* in, gw_dtype it, void* out, gw_dtype ot,
                          int n, int sign, hipStream_t s);
-gw_status launch_tau2omega(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it,
-                           void* out, gw_dtype ot, long long cols, hipStream_t s);
-gw_status launch_drain(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it,
+gw_status launch_tau2omega(const gw_cell* c, const void* T, int n_omega, int parity, const void* in,
+                           gw_dtype it, void* out, gw_dtype ot, long long cols, hipStream_t s);
+gw_status launch_drain(const gw_cell* c, const void* T, int n_omega, int parity, const void* in, gw_dtype it,
                        void* out, gw_dtype ot, int n, hipStream_t s);
 gw_status launch_polarizability(const gw_cell* c, const void* GR, void* P, double g, gw_precision p,
                                 hipStream_t s);

@@ -11,6 +11,8 @@
 // the separable R -> k sum in registers, then each of its 4 wavefronts computes
 // one 16-column tile over all frequencies and writes it back.  Each column is
 // read and written exactly once, so in == out (in-place) is safe.
+#include <type_traits>
+
 #include "cplx.h"
 #include "internal.h"
 
@@ -349,93 +351,166 @@ __global__ __launch_bounds__(512, 1) void drain_3m(const double2* __restrict__ T
   }
 }
 
-// Ping-pong variant: two streams of four wavefronts share T in LDS and own one y
-// buffer each (64 columns).  Between two barriers one stream runs its matrix phase
-// while the other stores its previous results, refills its y from the prefetch
-// registers and issues the loads of its chunk after next, so HBM traffic and MFMA
-// overlap inside one workgroup.  Stream s handles chunks 2 blockIdx + s + 2 k gridDim.
-template <int N1, int N2, int N3, int MT, class TI, class TO>
+// Ping-pong variant: two streams of four wavefronts share the transform matrix in LDS
+// and own one y buffer each (64 columns).  Between two barriers one stream runs its
+// matrix phase while the other stores its previous results, refills its y from the
+// prefetch registers and issues the loads of its chunk after next, so HBM traffic and
+// MFMA overlap inside one workgroup.  Stream s handles chunks 2 blockIdx + s + 2 k gridDim.
+//
+// SYM = false: general complex T as three real GEMMs (t1 = Tr yr, t2 = Ti yi,
+// t3 = (Tr + Ti)(yr + yi)).
+// SYM = true: T[m][N-1-i] = s conj(T[m][i]) (s = +1 for bosonic, -1 for fermionic
+// frequencies on a grid symmetric about beta/2).  Pairing tau_i with its mirror,
+//   sum_i T_mi y_i = sum_{i < N/2} [Tr_mi u_i + i Ti_mi v_i] (+ the middle point),
+//   u_i = y_i + s y_{N-1-i},  v_i = y_i - s y_{N-1-i},
+// so Re = A [u_r ; -v_i] and Im = A [u_i ; v_r] with one real matrix A whose K rows are
+// Tr_mi (row i, i <= (N-1)/2) and Ti_mi (row N-1-i, i < N/2; row N for the middle
+// point of an odd N): two real GEMMs instead of three.  A thread loads a row and its
+// mirror, forms u and v in registers (they commute with the R -> k sum) and writes
+// (u_r, u_i) to row i and (-v_i, v_r) to row N-1-i of y.
+template <int N1, int N2, int N3, int MT, bool SYM, class TI, class TO>
 __global__ __launch_bounds__(512, 1) void drain_pp(const double2* __restrict__ T, int n_omega, int n_tau,
-                                                   const TI* in, TO* out, long long n2, int CB,
+                                                   double sgn, const TI* in, TO* out, long long n2, int CB,
                                                    long long nchunks) {
   constexpr int NR = N1 * N2 * N3;
   constexpr int NCP = 64;                              // columns per stream chunk
   constexpr int PU = NR <= kPF ? kPF / NR : 1;          // (tau, element) columns per thread
+  constexpr int PV = SYM ? PU / 2 : PU;                 // loaded units (a row pair when SYM)
   extern __shared__ double2 lds[];
   const int tid = threadIdx.x;
   const int nt4 = (n_tau + 7) & ~7, ld_t = nt4 + 1;  // K rounded to 8: an even number of K steps
-  double2* Ts = lds;                                   // [16 MT][ld_t]
+  const int half = (n_tau + 1) / 2;                    // rows i <= mirror(i)
+  double2* Ts = lds;                                   // [16 MT][ld_t] complex, or real when SYM
+  double* As = reinterpret_cast<double*>(lds);
+  const int tsz = SYM ? (16 * MT * ld_t + 1) / 2 : 16 * MT * ld_t;
   const int stream = tid >> 8, stid = tid & 255;       // 256 threads per stream
-  double2* y = lds + 16 * MT * ld_t + stream * nt4 * NCP;
+  double2* y = lds + tsz + stream * nt4 * NCP;
   for (int i = tid; i < 16 * MT * ld_t; i += 512) {
     const int m = i / ld_t, t = i - m * ld_t;
-    Ts[i] = (m < n_omega && t < n_tau) ? T[(long long)m * n_tau + t] : make_double2(0.0, 0.0);
+    if constexpr (SYM) {
+      double a = 0.0;
+      if (m < n_omega) {
+        if (t < half) a = T[(long long)m * n_tau + t].x;
+        else if (t < n_tau) a = T[(long long)m * n_tau + (n_tau - 1 - t)].y;
+        else if (t == n_tau && (n_tau & 1)) a = T[(long long)m * n_tau + (half - 1)].y;
+      }
+      As[i] = a;
+    } else {
+      Ts[i] = (m < n_omega && t < n_tau) ? T[(long long)m * n_tau + t] : make_double2(0.0, 0.0);
+    }
   }
   const int ncol = NR * CB;
+  const int rows = (SYM && (n_tau & 1)) ? n_tau + 1 : n_tau;  // rows of y that fill() writes
   for (int idx = stid; idx < nt4 * NCP; idx += 256) {  // padding rows / columns stay zero
     const int t = idx / NCP, rc = idx - t * NCP;
-    if (t >= n_tau || rc >= ncol) y[idx] = make_double2(0.0, 0.0);
+    if (t >= rows || rc >= ncol) y[idx] = make_double2(0.0, 0.0);
   }
   const int lane = tid & 63, w = (tid >> 6) & 3, li = lane & 15, lk = lane >> 4;
   const int col = 16 * w + li;
   const int ksn = nt4 / 4;
   const long long stride = 2LL * gridDim.x;
   const long long first = 2LL * blockIdx.x + stream;
+  const int trows = SYM ? half : n_tau;  // leading rows of the units a thread loads
   TI raw[PU * NR];
   auto fetch = [&](long long ch) {
     const long long e0 = ch * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
 #pragma unroll
-    for (int u = 0; u < PU; ++u) {
+    for (int u = 0; u < PV; ++u) {
       const int p = stid + 256 * u, t = p / CB, c = p - t * CB;
-      const bool live = ch < nchunks && t < n_tau && c < cb;
+      const bool live = ch < nchunks && t < trows && c < cb;
 #pragma unroll
-      for (int R = 0; R < NR; ++R) raw[u * NR + R] = ldraw(in + ((long long)t * NR + R) * n2 + e0 + c, in, live);
+      for (int R = 0; R < NR; ++R) {
+        if constexpr (SYM) {
+          raw[(2 * u) * NR + R] = ldraw(in + ((long long)t * NR + R) * n2 + e0 + c, in, live);
+          raw[(2 * u + 1) * NR + R] = ldraw(in + ((long long)(n_tau - 1 - t) * NR + R) * n2 + e0 + c, in, live);
+        } else {
+          raw[u * NR + R] = ldraw(in + ((long long)t * NR + R) * n2 + e0 + c, in, live);
+        }
+      }
     }
   };
   auto fill = [&](long long ch) {
     const long long e0 = ch * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
 #pragma unroll
-    for (int u = 0; u < PU; ++u) {
+    for (int u = 0; u < PV; ++u) {
       const int p = stid + 256 * u, t = p / CB, c = p - t * CB;
-      if (t < n_tau) {
+      if (t < trows) {
         const bool live = c < cb;
-        double pr[NR], pi[NR];
+        if constexpr (SYM) {
+          const bool mid = t == n_tau - 1 - t;
+          double ur[NR], ui[NR], vr[NR], vi[NR];
 #pragma unroll
-        for (int R = 0; R < NR; ++R) {
-          const TI v = keep(raw[u * NR + R], live);
-          pr[R] = (double)v.x;
-          pi[R] = (double)v.y;
+          for (int R = 0; R < NR; ++R) {
+            const TI a = keep(raw[(2 * u) * NR + R], live), b = keep(raw[(2 * u + 1) * NR + R], live);
+            const double br = mid ? 0.0 : sgn * (double)b.x, bi = mid ? 0.0 : sgn * (double)b.y;
+            ur[R] = (double)a.x + br;
+            ui[R] = (double)a.y + bi;
+            vr[R] = (double)a.x - br;
+            vi[R] = (double)a.y - bi;
+          }
+          r2k_regs<N1, N2, N3>(ur, ui);
+          r2k_regs<N1, N2, N3>(vr, vi);
+          const int t2 = mid ? n_tau : n_tau - 1 - t;
+#pragma unroll
+          for (int q = 0; q < NR; ++q) {
+            y[t * NCP + q * CB + c] = make_double2(ur[q], ui[q]);
+            y[t2 * NCP + q * CB + c] = make_double2(-vi[q], vr[q]);
+          }
+        } else {
+          double pr[NR], pi[NR];
+#pragma unroll
+          for (int R = 0; R < NR; ++R) {
+            const TI v = keep(raw[u * NR + R], live);
+            pr[R] = (double)v.x;
+            pi[R] = (double)v.y;
+          }
+          r2k_regs<N1, N2, N3>(pr, pi);
+#pragma unroll
+          for (int q = 0; q < NR; ++q) y[t * NCP + q * CB + c] = make_double2(pr[q], pi[q]);
         }
-        r2k_regs<N1, N2, N3>(pr, pi);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) y[t * NCP + q * CB + c] = make_double2(pr[q], pi[q]);
       }
     }
   };
   d4 t1[MT], t2[MT], t3[MT];
   // Two named operand sets: the LDS reads of one K step are issued before the MFMAs of
   // the other, so a single wavefront keeps its SIMD's matrix pipe busy.
+  typedef typename std::conditional<SYM, double, double2>::type AT;
   auto matrix = [&]() {
 #pragma unroll
     for (int i = 0; i < MT; ++i) t1[i] = t2[i] = t3[i] = d4{0, 0, 0, 0};
-    double2 ya, yb, ta[MT], tb[MT];
-    auto load = [&](int ks, double2& yv, double2* tv) {
+    double2 ya, yb;
+    AT ta[MT], tb[MT];
+    auto load = [&](int ks, double2& yv, AT* tv) {
       const int tau = 4 * ks + lk;
       yv = y[tau * NCP + col];
 #pragma unroll
-      for (int i = 0; i < MT; ++i) tv[i] = Ts[(16 * i + li) * ld_t + tau];
-    };
-    auto mma = [&](const double2& yv, const double2* tv) {
-      const double ys = yv.x + yv.y;
-#pragma unroll
       for (int i = 0; i < MT; ++i) {
-        t1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].x, yv.x, t1[i], 0, 0, 0);
-        t2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].y, yv.y, t2[i], 0, 0, 0);
-        t3[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].x + tv[i].y, ys, t3[i], 0, 0, 0);
+        if constexpr (SYM)
+          tv[i] = As[(16 * i + li) * ld_t + tau];
+        else
+          tv[i] = Ts[(16 * i + li) * ld_t + tau];
       }
     };
+    auto mma = [&](const double2& yv, const AT* tv) {
+      if constexpr (SYM) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          t1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i], yv.x, t1[i], 0, 0, 0);
+          t2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i], yv.y, t2[i], 0, 0, 0);
+        }
+      } else {
+        const double ys = yv.x + yv.y;
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          t1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].x, yv.x, t1[i], 0, 0, 0);
+          t2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].y, yv.y, t2[i], 0, 0, 0);
+          t3[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[i].x + tv[i].y, ys, t3[i], 0, 0, 0);
+        }
+      }
+    };
+    constexpr int NM = SYM ? 2 * MT : 3 * MT;  // MFMAs per K step
     load(0, ya, ta);
     for (int ks = 0; ks < ksn; ks += 2) {  // ksn is even; the last read of ya is a spare one
       load(ks + 1, yb, tb);
@@ -444,9 +519,9 @@ __global__ __launch_bounds__(512, 1) void drain_pp(const double2* __restrict__ T
       mma(yb, tb);
       // keep this order: reads of one set, MFMAs of the other, reads, MFMAs
       __builtin_amdgcn_sched_group_barrier(0x100, MT + 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 3 * MT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, MT + 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 3 * MT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, NM, 0);
     }
   };
   auto store = [&](long long ch) {
@@ -460,8 +535,13 @@ __global__ __launch_bounds__(512, 1) void drain_pp(const double2* __restrict__ T
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int m = 16 * i + lk + 4 * j;
-            if (m < n_omega)
-              stc(out + ((long long)m * NR + q) * n2 + e0 + c, t1[i][j] - t2[i][j], t3[i][j] - t1[i][j] - t2[i][j]);
+            if (m < n_omega) {
+              if constexpr (SYM)
+                stc(out + ((long long)m * NR + q) * n2 + e0 + c, t1[i][j], t2[i][j]);
+              else
+                stc(out + ((long long)m * NR + q) * n2 + e0 + c, t1[i][j] - t2[i][j],
+                    t3[i][j] - t1[i][j] - t2[i][j]);
+            }
           }
       }
     }
@@ -543,32 +623,41 @@ void run_drain_3m(const double2* T, int n_omega, int n_tau, const TI* in, TO* ou
 }
 
 template <int N1, int N2, int N3, class TI, class TO>
-void run_drain(const double2* T, int n_omega, int n_tau, const TI* in, TO* out, long long n2, hipStream_t s) {
+void run_drain(const double2* T, int n_omega, int n_tau, int parity, const TI* in, TO* out, long long n2,
+               hipStream_t s) {
   constexpr int NR = N1 * N2 * N3;
   const int MT = (n_omega + 15) / 16;
   const int nt4 = (n_tau + 3) & ~3;
   // ping-pong kernel: two 64-column streams; needs whole (tau, element) columns per thread
-  {
+  if constexpr (NR <= kPF) {
+    const bool sym = parity != 0 && kPF / NR >= 2;
     const int CB = NR >= 64 ? 1 : 64 / NR;
     const int nt8 = (n_tau + 7) & ~7;
-    const size_t lds = (size_t)(16 * MT * (nt8 + 1) + 2 * nt8 * 64) * sizeof(double2);
-    const bool regs_ok = NR <= kPF && (long long)n_tau * CB <= (long long)(kPF / (NR <= kPF ? NR : 1)) * 256;
-    if (MT <= 4 && NR * CB <= 64 && lds <= 160 * 1024 && regs_ok && NR <= kPF) {
+    const size_t tsz = sym ? (size_t)(16 * MT * (nt8 + 1) + 1) / 2 : (size_t)16 * MT * (nt8 + 1);
+    const size_t lds = (tsz + 2 * (size_t)nt8 * 64) * sizeof(double2);
+    const int units = kPF / NR / (sym ? 2 : 1);                 // loads per thread
+    const long long need = (long long)(sym ? (n_tau + 1) / 2 : n_tau) * CB;
+    if (MT <= 4 && NR * CB <= 64 && lds <= 160 * 1024 && need <= (long long)units * 256) {
       const long long nchunks = (n2 + CB - 1) / CB;
       const long long grid = (nchunks + 1) / 2 < 256 ? (nchunks + 1) / 2 : 256;
-#define GWR_PP(mt)                                                                                     \
-  case mt:                                                                                             \
-    (void)hipFuncSetAttribute((const void*)drain_pp<N1, N2, N3, mt, TI, TO>,                           \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
-    hipLaunchKernelGGL((drain_pp<N1, N2, N3, mt, TI, TO>), dim3((unsigned)grid), dim3(512), lds, s, T, \
-                       n_omega, n_tau, in, out, n2, CB, nchunks);                                      \
-    return;
-      switch (MT) {
-        GWR_PP(1)
-        GWR_PP(2)
-        GWR_PP(3)
-        GWR_PP(4)
-        default: break;
+      const double sgn = parity < 0 ? -1.0 : 1.0;
+#define GWR_PP(mt, sy)                                                                                       \
+  if (MT == mt && sym == sy) {                                                                               \
+    (void)hipFuncSetAttribute((const void*)drain_pp<N1, N2, N3, mt, sy, TI, TO>,                             \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                         \
+    hipLaunchKernelGGL((drain_pp<N1, N2, N3, mt, sy, TI, TO>), dim3((unsigned)grid), dim3(512), lds, s, T,   \
+                       n_omega, n_tau, sgn, in, out, n2, CB, nchunks);                                       \
+    return;                                                                                                  \
+  }
+      GWR_PP(1, false)
+      GWR_PP(2, false)
+      GWR_PP(3, false)
+      GWR_PP(4, false)
+      if constexpr (kPF / NR >= 2) {
+        GWR_PP(1, true)
+        GWR_PP(2, true)
+        GWR_PP(3, true)
+        GWR_PP(4, true)
       }
 #undef GWR_PP
     }
@@ -611,12 +700,12 @@ bool mfma_ok(int n_tau, int n_omega) { return n_tau <= kDrainMaxTau && n_omega <
 
 // dispatch on the mesh; returns false if the mesh has no fused kernel
 template <class TI, class TO>
-bool drain_dispatch(const gw_cell* c, const double2* T, int n_omega, const TI* in, TO* out, long long n2,
-                    hipStream_t s) {
+bool drain_dispatch(const gw_cell* c, const double2* T, int n_omega, int parity, const TI* in, TO* out,
+                    long long n2, hipStream_t s) {
   const int a = c->mesh[0], b = c->mesh[1], d = c->mesh[2];
 #define GWR_DRAIN(x, y, z)                                                \
   if (a == x && b == y && d == z) {                                       \
-    run_drain<x, y, z>(T, n_omega, c->n_tau, in, out, n2, s);             \
+    run_drain<x, y, z>(T, n_omega, c->n_tau, parity, in, out, n2, s);     \
     return true;                                                          \
   }
   GWR_DRAIN(1, 1, 1)
@@ -631,46 +720,55 @@ bool drain_dispatch(const gw_cell* c, const double2* T, int n_omega, const TI* i
 }
 
 template <class TI, class TO>
-gw_status tau2omega_typed(const gw_cell* c, const double2* T, int n_omega, const TI* in, TO* out,
+gw_status tau2omega_typed(const gw_cell* c, const double2* T, int n_omega, int parity, const TI* in, TO* out,
                           long long cols, hipStream_t s) {
   if (mfma_ok(c->n_tau, n_omega))
-    run_drain<1, 1, 1>(T, n_omega, c->n_tau, in, out, cols, s);
+    run_drain<1, 1, 1>(T, n_omega, c->n_tau, parity, in, out, cols, s);
   else
     run_valu(T, n_omega, c->n_tau, in, out, cols, s);
   return check_launch("tau2omega");
 }
 
 template <class TI, class TO>
-gw_status drain_typed(const gw_cell* c, const double2* T, int n_omega, const TI* in, TO* out, int n,
+gw_status drain_typed(const gw_cell* c, const double2* T, int n_omega, int parity, const TI* in, TO* out, int n,
                       gw_dtype ot, hipStream_t s) {
   const long long n2 = (long long)n * n;
-  if (mfma_ok(c->n_tau, n_omega) && drain_dispatch(c, T, n_omega, in, out, n2, s)) return check_launch("drain");
+  if (mfma_ok(c->n_tau, n_omega) && drain_dispatch(c, T, n_omega, parity, in, out, n2, s))
+    return check_launch("drain");
   // two passes through `out`: needs room for n_tau rows there
   if ((const void*)in != (const void*)out && n_omega < c->n_tau)
     return fail(GW_ERR_UNSUPPORTED, "this mesh / grid needs n_omega >= n_tau or an in-place drain");
   gw_status st = launch_fourier(c, in, sizeof(TI) == 16 ? GW_C128 : GW_C64, out, ot, n, -1, s);
   if (st != GW_OK) return st;
-  return tau2omega_typed(c, T, n_omega, out, out, (long long)c->N_R * n2, s);
+  return tau2omega_typed(c, T, n_omega, parity, out, out, (long long)c->N_R * n2, s);
 }
 
 }  // namespace
 
-gw_status launch_tau2omega(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it, void* out,
-                           gw_dtype ot, long long cols, hipStream_t s) {
+gw_status launch_tau2omega(const gw_cell* c, const void* T, int n_omega, int parity, const void* in, gw_dtype it,
+                           void* out, gw_dtype ot, long long cols, hipStream_t s) {
   const double2* Td = (const double2*)T;
-  if (it == GW_C128 && ot == GW_C128) return tau2omega_typed(c, Td, n_omega, (const double2*)in, (double2*)out, cols, s);
-  if (it == GW_C128 && ot == GW_C64) return tau2omega_typed(c, Td, n_omega, (const double2*)in, (float2*)out, cols, s);
-  if (it == GW_C64 && ot == GW_C128) return tau2omega_typed(c, Td, n_omega, (const float2*)in, (double2*)out, cols, s);
-  return tau2omega_typed(c, Td, n_omega, (const float2*)in, (float2*)out, cols, s);
+  const int p = parity;
+  if (it == GW_C128 && ot == GW_C128)
+    return tau2omega_typed(c, Td, n_omega, p, (const double2*)in, (double2*)out, cols, s);
+  if (it == GW_C128 && ot == GW_C64)
+    return tau2omega_typed(c, Td, n_omega, p, (const double2*)in, (float2*)out, cols, s);
+  if (it == GW_C64 && ot == GW_C128)
+    return tau2omega_typed(c, Td, n_omega, p, (const float2*)in, (double2*)out, cols, s);
+  return tau2omega_typed(c, Td, n_omega, p, (const float2*)in, (float2*)out, cols, s);
 }
 
-gw_status launch_drain(const gw_cell* c, const void* T, int n_omega, const void* in, gw_dtype it, void* out,
-                       gw_dtype ot, int n, hipStream_t s) {
+gw_status launch_drain(const gw_cell* c, const void* T, int n_omega, int parity, const void* in, gw_dtype it,
+                       void* out, gw_dtype ot, int n, hipStream_t s) {
   const double2* Td = (const double2*)T;
-  if (it == GW_C128 && ot == GW_C128) return drain_typed(c, Td, n_omega, (const double2*)in, (double2*)out, n, ot, s);
-  if (it == GW_C128 && ot == GW_C64) return drain_typed(c, Td, n_omega, (const double2*)in, (float2*)out, n, ot, s);
-  if (it == GW_C64 && ot == GW_C128) return drain_typed(c, Td, n_omega, (const float2*)in, (double2*)out, n, ot, s);
-  return drain_typed(c, Td, n_omega, (const float2*)in, (float2*)out, n, ot, s);
+  const int p = parity;
+  if (it == GW_C128 && ot == GW_C128)
+    return drain_typed(c, Td, n_omega, p, (const double2*)in, (double2*)out, n, ot, s);
+  if (it == GW_C128 && ot == GW_C64)
+    return drain_typed(c, Td, n_omega, p, (const double2*)in, (float2*)out, n, ot, s);
+  if (it == GW_C64 && ot == GW_C128)
+    return drain_typed(c, Td, n_omega, p, (const float2*)in, (double2*)out, n, ot, s);
+  return drain_typed(c, Td, n_omega, p, (const float2*)in, (float2*)out, n, ot, s);
 }
 
 }  // namespace gwr

@@ -35,7 +35,8 @@ def test_validation_without_device():
     assert lib.gw_polarizability(None, None, None, 2.0, 0, None) == g.GW_ERR_ARG
     assert lib.gw_self_energy(None, None, None, None, 0, None) == g.GW_ERR_ARG
     assert lib.gw_fourier_k2r(None, None, 0, None, 0, 0, None) == g.GW_ERR_ARG
-    assert lib.gw_drain(None, None, 48, None, 0, None, 0, 1, None) == g.GW_ERR_ARG
+    assert lib.gw_drain(None, None, 48, 0, None, 0, None, 0, 1, None) == g.GW_ERR_ARG
+    assert lib.gw_tau2omega(None, None, 48, 1, None, 0, None, 0, 1, None) == g.GW_ERR_ARG
     assert lib.gw_density(None, None, 0, 0, 2.0, None, None) == g.GW_ERR_ARG
     h = ctypes.c_void_p()
     sp = np.zeros(2, dtype=np.int32)
@@ -80,3 +81,16 @@ def test_host_matsubara_matrix_nonuniform_grid():
     assert np.max(np.abs(T - To)) / np.max(np.abs(To)) < 1e-11
     with pytest.raises(g.GWError):
         g.gw_tau2omega_matrix(tau[::-1].copy(), w)
+
+
+@pytest.mark.parametrize("kind,parity", [("bosonic", 1), ("fermionic", -1)])
+@pytest.mark.parametrize("n", [48, 7, 2])
+def test_host_matsubara_matrix_has_the_declared_mirror_parity(kind, parity, n):
+    """T[m][n-1-i] = parity * conj(T[m][i]) on a grid symmetric about beta / 2 (the
+    precondition of the two-GEMM drain), uniform and clustered grids alike."""
+    import paper_1911_05633_amd as g
+    beta = 100.0
+    for tau in (beta * np.arange(n) / (n - 1), 0.5 * beta * (1 - np.cos(np.pi * np.arange(n) / (n - 1)))):
+        T = g.gw_tau2omega_matrix(tau, g.matsubara(n + 3, beta, kind))
+        mirror = parity * np.conj(T[:, ::-1])
+        assert np.max(np.abs(T - mirror)) <= 1e-13 * np.max(np.abs(T))

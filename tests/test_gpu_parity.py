@@ -144,17 +144,19 @@ def test_fp32_storage_paths(name):
 
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("basis", [0, 1])
-def test_tau2omega_and_drain(name, basis):
+@pytest.mark.parametrize("use_parity", [False, True])
+def test_tau2omega_and_drain(name, basis, use_parity):
     import torch
     import paper_1911_05633_amd as g
     d = case(name)
     spec = d["spec"]
-    print(f"[omega] {name} basis {basis}", flush=True)
+    print(f"[omega] {name} basis {basis} parity {use_parity}", flush=True)
     cell = gpu_cell(d)
     n = spec.N_orb if basis == 0 else spec.N_pb
     F = sc.random_complex((spec.n_tau, spec.N_R, n, n), seed=11 + basis)
     tau = sc.tau_grid(spec)
     kind = "fermionic" if basis == 0 else "bosonic"
+    par = (-1 if kind == "fermionic" else 1) if use_parity else 0
     w = g.matsubara(spec.n_tau, spec.beta, kind)
     T = g.gw_tau2omega_matrix(tau, w)
     To = oracle.filon_matrix(tau, w)
@@ -162,19 +164,23 @@ def test_tau2omega_and_drain(name, basis):
     ref_d = oracle.apply_tau_to_omega(To, oracle.r_to_k(F, spec.mesh))
     Fd, Td = dev(F), dev(T)
     out = torch.empty_like(Fd)
-    g.gw_tau2omega(cell, Td, Fd, out, basis=basis)
+    g.gw_tau2omega(cell, Td, Fd, out, basis=basis, parity=par)
     assert relmax(host(out), ref_w) < 1e-12
-    g.gw_drain(cell, Td, Fd, out, basis=basis)
+    g.gw_drain(cell, Td, Fd, out, basis=basis, parity=par)
     assert relmax(host(out), ref_d) < 1e-12
     # in place, fewer frequencies than tau points
     Td8 = dev(T[:8].copy())
     F2 = Fd.clone()
-    g.gw_drain(cell, Td8, F2, F2, basis=basis)
+    g.gw_drain(cell, Td8, F2, F2, basis=basis, parity=par)
     assert relmax(host(F2)[:8], ref_d[:8]) < 1e-12
     # complex64 in, complex128 out
     out2 = torch.empty_like(Fd)
-    g.gw_drain(cell, Td, Fd.to(torch.complex64), out2, basis=basis)
+    g.gw_drain(cell, Td, Fd.to(torch.complex64), out2, basis=basis, parity=par)
     assert relmax(host(out2), ref_d) < 1e-6
+    # complex64 in and out, in place (the mixed path's P drain)
+    F3 = Fd.to(torch.complex64)
+    g.gw_drain(cell, Td, F3, F3, basis=basis, parity=par)
+    assert relmax(host(F3).astype(np.complex128), ref_d) < 1e-6
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -213,8 +219,8 @@ def test_chained_path_fp64(name):
     tau = sc.tau_grid(spec)
     nu = g.matsubara(spec.n_tau, spec.beta, "bosonic")
     wf = g.matsubara(spec.n_tau, spec.beta, "fermionic")
-    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, nu)), P, P, basis=1)
-    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, wf)), S, S, basis=0)
+    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, nu)), P, P, basis=1, parity=1)
+    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, wf)), S, S, basis=0, parity=-1)
     Pq = oracle.polarizability_q(d["Gk"], spec, d["C"], spec.spin)
     Sk = oracle.self_energy_k(d["Gk"], d["WR"], spec, d["C"])
     Pw = oracle.apply_tau_to_omega(oracle.filon_matrix(tau, oracle.bosonic_frequencies(spec.n_tau, spec.beta)), Pq)
@@ -271,8 +277,8 @@ def test_chained_path_mixed(name):
     tau = sc.tau_grid(spec)
     nu = g.matsubara(spec.n_tau, spec.beta, "bosonic")
     wf = g.matsubara(spec.n_tau, spec.beta, "fermionic")
-    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, nu)), P, P, basis=1)
-    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, wf)), S, S, basis=0)
+    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, nu)), P, P, basis=1, parity=1)
+    g.gw_drain(cell, dev(g.gw_tau2omega_matrix(tau, wf)), S, S, basis=0, parity=-1)
     n = torch.zeros(1, dtype=torch.float64, device="cuda")
     g.gw_density(cell, Gk, spec.spin, n, space=1)
     Pq = oracle.polarizability_q(d["Gk"], spec, d["C"], spec.spin)

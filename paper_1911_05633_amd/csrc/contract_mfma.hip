@@ -65,7 +65,6 @@ struct Mma<float> {
 
 constexpr int kPL = 48;       // padded pair count handled here (n <= 9)
 constexpr int kKA = kPL / 4;  // K steps over pairs
-constexpr int kTB = kPL / 8;  // 16-row tiles of (pair, part)
 constexpr int kMP = 64;       // padded product functions handled here (m <= 64)
 constexpr int kJT = kMP / 16;
 constexpr int kKJ = kMP / 4;
@@ -114,6 +113,7 @@ struct PairArgs {
 // polarizability
 // ---------------------------------------------------------------------------
 constexpr int kQS = 56;      // LDS row stride of Q (complex): 4 consecutive rows land 32 banks apart
+constexpr int kQE = (kPL * kPL + 255) / 256;  // Q entries per thread
 constexpr int kCS = kPL + 1; // LDS row stride of C~_B (real): 16 consecutive rows hit distinct banks
 
 template <class RT, class CT>
@@ -134,6 +134,24 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
     Cb[J * kCS + pp] = CpB[i];
   }
   const int nKA = q.nppA / 4, nTB = q.nppB / 8, nJT = (q.mB + 15) / 16, nIT = q.mpA / 16;
+  __syncthreads();  // pair tables staged
+  // per-thread Q entries: packed (a, b, c, d) of p = {a, b} and p' = {c, d}, or all ones
+  // outside the live pairs, and the LDS offset of the entry
+  unsigned qpk[kQE];
+  int qoff[kQE];
+#pragma unroll
+  for (int e = 0; e < kQE; ++e) {
+    const int i = tid + 256 * e;
+    const int p = i / q.nppB, pp = i - p * q.nppB;
+    qoff[e] = p * kQS + pp;
+    qpk[e] = (i < q.nppA * q.nppB && p < q.npA && pp < q.npB)
+                 ? (unsigned)ta[p] | ((unsigned)tb[p] << 8) | ((unsigned)tc[pp] << 16) | ((unsigned)td[pp] << 24)
+                 : 0xffffffffu;
+  }
+  // each wavefront owns at most one I tile (m_pad <= 64): its C~_A operands are loaded once
+  RT b1[kKA];
+#pragma unroll
+  for (int ks = 0; ks < kKA; ++ks) b1[ks] = (w < nIT && ks < nKA) ? CpA[(16 * w + li) * q.nppA + 4 * ks + lk] : RT(0);
   int rg, rj;
   M::split(li, rg, rj);
   const int row_pp = 4 * (rj >> 1) + rg, row_part = rj & 1;
@@ -189,39 +207,42 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
     const int pA = q.pb_off[k.A], pB = q.pb_off[k.B];
     const bool more = blk + gridDim.x < q.nblocks;
     if (more) fetch(decode(blk + gridDim.x));
-    // Q over unordered pairs (zero outside the live pairs)
-    for (int i = tid; i < q.nppA * q.nppB; i += 256) {
-      const int p = i / q.nppB, pp = i - p * q.nppB;
-      RT qr = 0, qi = 0;
-      if (p < q.npA && pp < q.npB) {
-        const int a = ta[p], bq = tb[p], c = tc[pp], d = td[pp];
-        const int nB = q.nB, nA = q.nA;
+    // Q over unordered pairs (zero outside the live pairs); the pair tables of this
+    // thread's entries are held in registers
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int c1 = s ? d : c, d1 = s ? c : d;
-          if (s == 1 && c == d) break;
-          CR x = Xs[a * nB + c1], y = Ys[d1 * nA + bq];
-          qr += x.x * y.x - x.y * y.y;
-          qi += x.x * y.y + x.y * y.x;
-          if (a != bq) {
-            x = Xs[bq * nB + c1];
-            y = Ys[d1 * nA + a];
+    for (int e = 0; e < kQE; ++e) {
+      const int i = tid + 256 * e;
+      if (i < q.nppA * q.nppB) {
+        RT qr = 0, qi = 0;
+        const unsigned pk = qpk[e];
+        if (pk != 0xffffffffu) {
+          const int a = pk & 0xff, bq = (pk >> 8) & 0xff, c = (pk >> 16) & 0xff, d = pk >> 24;
+          const int nB = q.nB, nA = q.nA;
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int c1 = s2 ? d : c, d1 = s2 ? c : d;
+            if (s2 == 1 && c == d) break;
+            CR x = Xs[a * nB + c1], y = Ys[d1 * nA + bq];
             qr += x.x * y.x - x.y * y.y;
             qi += x.x * y.y + x.y * y.x;
+            if (a != bq) {
+              x = Xs[bq * nB + c1];
+              y = Ys[d1 * nA + a];
+              qr += x.x * y.x - x.y * y.y;
+              qi += x.x * y.y + x.y * y.x;
+            }
           }
         }
+        Qs[qoff[e]] = mk<RT>(qr, qi);
       }
-      Qs[p * kQS + pp] = mk<RT>(qr, qi);
     }
     __syncthreads();
     if (more) stage();
 
     CT* Pd = P + ((long long)t * q.NR + R) * slp;
     CT* Pm = P + ((long long)tm * q.NR + mR) * slp;
-    for (int it = w; it < nIT; it += 4) {
-      RT b1[kKA];
-#pragma unroll
-      for (int ks = 0; ks < kKA; ++ks) b1[ks] = ks < nKA ? CpA[(16 * it + li) * q.nppA + 4 * ks + lk] : RT(0);
+    if (w < nIT) {
+      const int it = w;
       typename M::acc acc2[kJT][2];
 #pragma unroll
       for (int Jt = 0; Jt < kJT; ++Jt) acc2[Jt][0] = acc2[Jt][1] = typename M::acc{0, 0, 0, 0};
@@ -449,6 +470,193 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   }
 }
 
+// ---------------------------------------------------------------------------
+// self-energy, FP32 storage.  Same contraction as s_mfma, restructured so that no wave
+// waits for HBM inside a block: the whole W^R(tau)[A, B] block (<= 64 x 64) sits in LDS
+// (row stride 66 complex: the 64 lanes of an A-operand read hit distinct bank pairs)
+// and the next block's W is loaded into registers while this one is multiplied, a whole
+// block ahead.  C~_A is kept in LDS (row stride 52 floats: conflict-free GEMM2 reads),
+// C~_B in registers; the first product of I tile it+1 is issued before the second
+// product of tile it.  The FP64 unfold forms the unordered-pair indices arithmetically.
+// ---------------------------------------------------------------------------
+constexpr int kS32Threads = 192;
+constexpr int kW32S = 66;                                            // W row stride (complex)
+constexpr int kW32PF = (kMP * kMP + kS32Threads - 1) / kS32Threads;  // prefetched W values per thread
+constexpr int kCA32S = 52;                                           // C~_A row stride (floats)
+constexpr int kIT32 = kMP / 16;
+
+// NIT = m_pad(A) / 16, NKJ = m_pad(B) / 4, NMT = np_pad(A) / 16 are compile-time so that
+// every operand array stays in registers.
+template <int NIT, int NKJ, int NMT>
+__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_mfma32(
+    const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
+    const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
+  __shared__ __align__(16) float2 Ub[kMP * kW32S];  // W block, then the K block
+  __shared__ float Ca[kMP * kCA32S];
+  __shared__ float2 Xs[81];
+  float2* Wb = Ub;
+  float2* Ks = Ub;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  constexpr int nIT = NIT, nKJ = NKJ, nMT = NMT;
+  const bool mm = 16 * w < q.nppB;  // this wavefront has pairs of B
+  for (int i = tid; i < kMP * kCA32S; i += kS32Threads) {
+    const int I = i / kCA32S, p = i - I * kCA32S;
+    Ca[i] = (I < q.mpA && p < q.nppA) ? CpA[I * q.nppA + p] : 0.f;
+  }
+  float b1[kKJ];
+#pragma unroll
+  for (int ks = 0; ks < kKJ; ++ks) b1[ks] = (mm && ks < nKJ) ? CpB[(4 * ks + lk) * q.nppB + 16 * w + li] : 0.f;
+  const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+  const int half_a = (q.nA + 1) / 2;
+  const int uo = tid >> 1, uh = tid & 1;
+  struct Blk {
+    int t, R, A, B;
+  };
+  auto decode = [&](long long b) {
+    Blk o;
+    const int iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    const int iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    o.R = (int)(b % q.NR);
+    o.t = (int)(b / q.NR);
+    o.A = q.atomsA[iA];
+    o.B = q.atomsB[iB];
+    return o;
+  };
+  // W rows r = w + 3 u (64 consecutive elements of a row per wavefront), column = lane
+  float2 wreg[kW32PF];
+  float2 xr;
+  const bool lane_ok = lane < q.mB;
+  auto fetch = [&](const Blk& k) {
+    const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(q.pb_off[k.A] + w) * q.Np +
+                      q.pb_off[k.B] + lane;
+    const long long step = 3LL * q.Np;
+#pragma unroll
+    for (int u = 0; u < kW32PF; ++u) {
+      wreg[u] = ldraw(p, WR, lane_ok && w + 3 * u < q.mA);
+      p += step;
+    }
+  };
+  const bool xok = tid < q.nA * q.nB;
+  auto fetch_x = [&](const Blk& k) {
+    const int a = tid / q.nB, c = tid - a * q.nB;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
+               GR, xok);
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < kW32PF; ++u) {
+      const int r = w + 3 * u;
+      if (r < kMP) Wb[r * kW32S + lane] = keep(wreg[u], r < q.mA && lane_ok);
+    }
+    if (xok) Xs[tid] = xr;
+  };
+  auto load_ca = [&](int it, float (&ca)[4][3]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) ca[j][m] = Ca[(16 * it + 4 * lk + j) * kCA32S + 16 * m + li];
+  };
+  auto gemm1 = [&](int it, f4& zr, f4& zi) {
+    zr = f4{0, 0, 0, 0};
+    zi = f4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < kKJ; ++ks)
+      if (ks < nKJ) {
+        const float2 wv = Wb[(16 * it + li) * kW32S + 4 * ks + lk];
+        zr = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, b1[ks], zr, 0, 0, 0);
+        zi = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, b1[ks], zi, 0, 0, 0);
+      }
+  };
+
+  if (blockIdx.x < q.nblocks) {
+    const Blk k0 = decode(blockIdx.x);
+    fetch(k0);
+    fetch_x(k0);
+    stash();
+  }
+  __syncthreads();
+  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
+    const Blk k = decode(blk);
+    const int oA = q.orb_off[k.A], oB = q.orb_off[k.B];
+    const bool more = blk + gridDim.x < q.nblocks;
+    if (more) {
+      const Blk kn = decode(blk + gridDim.x);
+      fetch(kn);
+      fetch_x(kn);
+    }
+    f4 acc2[3][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = f4{0, 0, 0, 0};
+    if (mm) {
+      f4 zr0, zi0, zr1, zi1;
+      float ca[4][3];
+      gemm1(0, zr0, zi0);
+#pragma unroll
+      for (int it = 0; it < kIT32; ++it) {
+        if (it < nIT) {
+          load_ca(it, ca);
+          if (it + 1 < nIT) gemm1(it + 1, zr1, zi1);
+          // K_part[p][p'] += C~_A[I][p] Z_part[I][p'], K steps I = 16 it + 4 lk + j
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+              if (m < nMT) {
+                acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[j][m], zr0[j], acc2[m][0], 0, 0, 0);
+                acc2[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[j][m], zi0[j], acc2[m][1], 0, 0, 0);
+              }
+          zr0 = zr1;
+          zi0 = zi1;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    __syncthreads();  // every wavefront is done with W
+    if (mm) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        if (m < nMT)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            Ks[(16 * m + 4 * lk + j) * kKS + 16 * w + li] = make_float2(acc2[m][0][j], acc2[m][1][j]);
+    }
+    __syncthreads();
+    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'} in FP64; the two halves of the a'
+    // range sit in neighbouring lanes and are combined with one exchange
+    double sr = 0, si = 0;
+    const bool live = uo < q.nA * q.nB;
+    if (live) {
+      const int a = uo / q.nB, bb = uo - a * q.nB;
+      const int a0 = uh ? half_a : 0, a1 = uh ? q.nA : half_a;
+      int pb[9];
+#pragma unroll
+      for (int bp = 0; bp < 9; ++bp) pb[bp] = bp < q.nB ? pair_index(bb, bp, q.nB) : 0;
+      for (int ap = a0; ap < a1; ++ap) {
+        const float2* Kr = Ks + pair_index(a, ap, q.nA) * kKS;
+        const float2* Xr = Xs + ap * q.nB;
+#pragma unroll
+        for (int bp = 0; bp < 9; ++bp)
+          if (bp < q.nB) {
+            const float2 kv = Kr[pb[bp]], x = Xr[bp];
+            sr += (double)kv.x * x.x - (double)kv.y * x.y;
+            si += (double)kv.x * x.y + (double)kv.y * x.x;
+          }
+      }
+    }
+    sr += __shfl_xor(sr, 1);
+    si += __shfl_xor(si, 1);
+    __syncthreads();  // K and X no longer read
+    if (more) stash();
+    if (live && uh == 0) {
+      const int a = uo / q.nB, bb = uo - a * q.nB;
+      S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
+    }
+    __syncthreads();
+  }
+}
+
 PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, int n_half) {
   PairArgs q;
   q.nA = A.n;
@@ -505,6 +713,12 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);
+  else if (A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)  // n = 9 with m in (48, 64]: the Si-like species
+    hipLaunchKernelGGL((s_mfma32<4, 16, 3>), dim3(grid_for(q.nblocks)), dim3(kS32Threads), 0, s,
+                       (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+  else if (A.m_pad == 16 && B.m_pad == 16 && A.np_pad == 16)  // up to 5 orbitals and 16 product functions
+    hipLaunchKernelGGL((s_mfma32<1, 4, 1>), dim3(grid_for(q.nblocks)), dim3(kS32Threads), 0, s,
+                       (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   else
     hipLaunchKernelGGL((s_mfma<float, float2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);

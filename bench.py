@@ -28,6 +28,50 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
 HBM_PEAK = 8.0e12
 
+# HBM bytes per launch of a kernel from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE of
+# the kernel, each divided by the same counter's reading per byte of a plain device copy;
+# the summaries are in profiles/).  Keyed by (kernel, precision); valid only while the
+# source file that defines the kernel has the recorded SHA-256 prefix, else reported null.
+TRAFFIC = {
+    ("Sigma", "fp32"): {"bytes": 62.62e9 + 3.35e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
+                        "sha256": "f4c650e2038e2010"},
+    ("P", "fp32"): {"bytes": 3.31e9 + 57.53e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
+                    "sha256": "f4c650e2038e2010"},
+    ("drain_P", "fp32"): {"bytes": 64.73e9 + 78.24e9, "source": "paper_1911_05633_amd/csrc/omega_kernels.h",
+                          "sha256": "c18cd167d389bbc1"},
+    ("k2r", "fp32"): {"bytes": 2.58e9 + 1.29e9, "source": "paper_1911_05633_amd/csrc/fourier.hip",
+                      "sha256": "a5af6e76c96c7ef9"},
+}
+
+
+def _source_hash(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel, prec):
+    rec = TRAFFIC.get((kernel, prec))
+    if rec is None:
+        return None
+    try:
+        if _source_hash(rec["source"]) != rec["sha256"]:
+            return None
+    except OSError:
+        return None
+    return rec["bytes"]
+
+
+def copy_reference(gib, torch, log):
+    """One plain device copy of `gib` GiB (the reference for scaling the HBM byte counters)."""
+    n = int(gib * 2**30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy reference: {n * 8} bytes read and {n * 8} bytes written")
+
 
 def pair_flops(spec):
     """Algorithmic P and Sigma flops per (tau, R) slice: sum over atom pairs of the cheapest
@@ -253,6 +297,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the step benchmark")
+    ap.add_argument("--copy-ref", type=float, default=0.0, metavar="GIB",
+                    help="only run one plain device copy of GIB GiB (counter reference) and exit")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -268,6 +314,9 @@ def main():
     import synthcell as sc
     import paper_1911_05633_amd as g
 
+    if args.copy_ref > 0:
+        copy_reference(args.copy_ref, torch, log)
+        return
     if args.serve:
         serve_bench(args, torch, log)
         return
@@ -302,7 +351,7 @@ def main():
                                f"mesh {'x'.join(map(str, spec.mesh))}, n_tau {spec.n_tau}, beta {spec.beta}",
                    "precision": args.prec, "per_kernel_ms": per, "electron_count": n_val},
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / scale, "peak": peak / scale,
-                     "unit": unit, "frac": achieved / peak, "traffic": None},
+                     "unit": unit, "frac": achieved / peak, "traffic": traffic_for(dom, args.prec)},
     }
     if not args.no_cpu:
         out["cpu_baseline"], out["config"]["error_vs_oracle"] = cpu_baseline(spec, d, fp, fs, log, g, cell,

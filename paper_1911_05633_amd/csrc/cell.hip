@@ -92,6 +92,9 @@ gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom,
     delete c;
     return fail(GW_ERR_HIP, "hipGetDevice failed");
   }
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      c->n_cu < 1)
+    c->n_cu = 256;
   c->n_atoms = n_atoms;
   c->n_species = n_species;
   c->species.assign(species_of_atom, species_of_atom + n_atoms);

@@ -570,19 +570,25 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       }
   };
 
-  if (blockIdx.x < q.nblocks) {
-    const Blk k0 = decode(blockIdx.x);
+  // Each workgroup walks one contiguous range of blocks (B fastest): consecutive blocks
+  // read neighbouring column ranges of the same W rows, so the cache lines they share
+  // are still in this XCD's L2 when the next block is fetched.
+  const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
+  const long long bbeg = (long long)blockIdx.x * per;
+  const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
+  if (bbeg < bend) {
+    const Blk k0 = decode(bbeg);
     fetch(k0);
     fetch_x(k0);
     stash();
   }
   __syncthreads();
-  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
+  for (long long blk = bbeg; blk < bend; ++blk) {
     const Blk k = decode(blk);
     const int oA = q.orb_off[k.A], oB = q.orb_off[k.B];
-    const bool more = blk + gridDim.x < q.nblocks;
+    const bool more = blk + 1 < bend;
     if (more) {
-      const Blk kn = decode(blk + gridDim.x);
+      const Blk kn = decode(blk + 1);
       fetch(kn);
       fetch_x(kn);
     }
@@ -710,15 +716,18 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
   const PairArgs q = make_args(c, A, B, c->n_tau);
   if (q.nblocks == 0) return;
   const unsigned threads = kSThreads;
+  // s_mfma32 holds three workgroups per compute unit: two full rounds of them
+  const long long g32 = 6LL * c->n_cu;
+  const unsigned grid32 = (unsigned)(q.nblocks < g32 ? q.nblocks : g32);
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);
   else if (A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)  // n = 9 with m in (48, 64]: the Si-like species
-    hipLaunchKernelGGL((s_mfma32<4, 16, 3>), dim3(grid_for(q.nblocks)), dim3(kS32Threads), 0, s,
-                       (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+    hipLaunchKernelGGL((s_mfma32<4, 16, 3>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
+                       (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (A.m_pad == 16 && B.m_pad == 16 && A.np_pad == 16)  // up to 5 orbitals and 16 product functions
-    hipLaunchKernelGGL((s_mfma32<1, 4, 1>), dim3(grid_for(q.nblocks)), dim3(kS32Threads), 0, s,
-                       (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+    hipLaunchKernelGGL((s_mfma32<1, 4, 1>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
+                       (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   else
     hipLaunchKernelGGL((s_mfma<float, float2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);

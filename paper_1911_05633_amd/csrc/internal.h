@@ -40,6 +40,7 @@ struct PairTables {
 
 struct gw_cell {
   int device = 0;
+  int n_cu = 256;                      // compute units of the device (sizes persistent grids)
   int n_atoms = 0, n_species = 0;
   std::vector<int> species;            // per atom
   std::vector<int> n_orb, n_pb;        // per species

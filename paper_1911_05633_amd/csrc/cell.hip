@@ -170,6 +170,10 @@ gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom,
     if ((st = upload(c, &d.Cpair, cp.data(), cp.size())) != GW_OK) break;
     if ((st = upload(c, &d.Cpair32, cp32.data(), cp32.size())) != GW_OK) break;
     if ((st = upload(c, &d.atoms_dev, d.atoms.data(), d.atoms.size())) != GW_OK) break;
+    std::vector<int2> offs(d.atoms.size(), make_int2(0, 0));
+    for (size_t i = 0; i < d.atoms.size(); ++i)
+      if (d.atoms[i] >= 0) offs[i] = make_int2(c->pb_off[d.atoms[i]], c->orb_off[d.atoms[i]]);
+    if ((st = upload(c, &d.offs_dev, offs.data(), offs.size())) != GW_OK) break;
     if (d.atoms[0] < 0) d.atoms.clear();
   }
   if (st == GW_OK) st = upload(c, &c->minusR_dev, c->minusR.data(), c->minusR.size());

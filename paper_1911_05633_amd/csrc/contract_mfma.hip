@@ -102,6 +102,8 @@ struct PairArgs {
   int cntA;
   const int* atomsB;
   int cntB;
+  const int2* offsA;  // per atom of species A (B): (first product function, first orbital)
+  const int2* offsB;
   const int* orb_off;
   const int* pb_off;
   const int* minusR;
@@ -116,7 +118,9 @@ constexpr int kQS = 56;      // LDS row stride of Q (complex): 4 consecutive row
 constexpr int kQE = (kPL * kPL + 255) / 256;  // Q entries per thread
 constexpr int kCS = kPL + 1; // LDS row stride of C~_B (real): 16 consecutive rows hit distinct banks
 
-template <class RT, class CT>
+// SH selects compile-time tile counts (no per-MFMA guards): 1 = np_pad 48 / m_pad 64 on both
+// atoms (9 orbitals, 49..64 product functions), 2 = np_pad 16 / m_pad 16; 0 = read from q.
+template <class RT, class CT, int SH>
 __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* __restrict__ P,
                                                  const RT* __restrict__ CpA, const RT* __restrict__ CpB,
                                                  const PairArgs q, double g) {
@@ -133,7 +137,10 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
     const int J = i / q.nppB, pp = i - J * q.nppB;
     Cb[J * kCS + pp] = CpB[i];
   }
-  const int nKA = q.nppA / 4, nTB = q.nppB / 8, nJT = (q.mB + 15) / 16, nIT = q.mpA / 16;
+  const int nKA = SH == 1 ? 12 : SH == 2 ? 4 : q.nppA / 4;
+  const int nTB = SH == 1 ? 6 : SH == 2 ? 2 : q.nppB / 8;
+  const int nJT = SH == 1 ? 4 : SH == 2 ? 1 : (q.mB + 15) / 16;
+  const int nIT = SH == 1 ? 4 : SH == 2 ? 1 : q.mpA / 16;
   __syncthreads();  // pair tables staged
   // per-thread Q entries: packed (a, b, c, d) of p = {a, b} and p' = {c, d}, or all ones
   // outside the live pairs, and the LDS offset of the entry
@@ -157,20 +164,26 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   const int row_pp = 4 * (rj >> 1) + rg, row_part = rj & 1;
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
   const RT* Qd = reinterpret_cast<const RT*>(Qs);
+  // Blocks are walked in one contiguous range per workgroup; (tau, R, iA, iB) advance by
+  // counting (B fastest) and the atom offsets come from the per-species (pb, orb) tables,
+  // the entries of block b + 2 being loaded while block b is multiplied.
+  __shared__ int mRs[kMaxR];
+  for (int i = tid; i < q.NR; i += 256) mRs[i] = q.minusR[i];
   struct Blk {
-    int t, R, A, B;
+    int t, R, iA, iB;
+    int2 oa, ob;  // (first product function, first orbital) of atoms A and B
   };
-  auto decode = [&](long long b) {
-    Blk o;
-    const int iB = (int)(b % q.cntB);
-    b /= q.cntB;
-    const int iA = (int)(b % q.cntA);
-    b /= q.cntA;
-    o.R = (int)(b % q.NR);
-    o.t = (int)(b / q.NR);
-    o.A = q.atomsA[iA];
-    o.B = q.atomsB[iB];
-    return o;
+  auto advance = [&](Blk& k) {
+    if (++k.iB == q.cntB) {
+      k.iB = 0;
+      if (++k.iA == q.cntA) {
+        k.iA = 0;
+        if (++k.R == q.NR) {
+          k.R = 0;
+          ++k.t;
+        }
+      }
+    }
   };
   // the X and Y tiles of the next block are loaded into registers (one element per thread,
   // n_A n_B <= 81 < 256) while the current block is on the matrix cores
@@ -178,11 +191,10 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   const bool xok = tid < q.nA * q.nB;
   auto fetch = [&](const Blk& k) {
     const int a = tid / q.nB, c = tid - a * q.nB;
-    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
-               GR, xok);
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
     const int d = tid / q.nA, bb = tid - d * q.nA;
-    yr = ldraw(GR + ((long long)(q.n_tau - 1 - k.t) * q.NR + q.minusR[k.R]) * sl +
-                   (long long)(q.orb_off[k.B] + d) * q.No + q.orb_off[k.A] + bb,
+    yr = ldraw(GR + ((long long)(q.n_tau - 1 - k.t) * q.NR + mRs[k.R]) * sl + (long long)(k.ob.y + d) * q.No +
+                   k.oa.y + bb,
                GR, xok);
   };
   auto stage = [&]() {
@@ -191,22 +203,46 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
       Ys[tid] = mk<RT>((double)yr.x, (double)yr.y);
     }
   };
-  // Order per block: issue the next block's G loads; form Q from this block's tiles;
-  // barrier; stage the next tiles into LDS (loads issued a Q formation earlier, before
-  // any of this block's stores); matrix phase and stores; barrier.
-  if (blockIdx.x < q.nblocks) {
-    fetch(decode(blockIdx.x));
+  // Order per block: issue the G loads of the next block; form Q from this block's tiles;
+  // barrier; matrix phase and stores; stage the next tiles into LDS (their loads were
+  // issued a whole block earlier); barrier.
+  const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
+  const long long bbeg = (long long)blockIdx.x * per;
+  const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
+  Blk cur;
+  {
+    long long b = bbeg < q.nblocks ? bbeg : 0;
+    cur.iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    cur.iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    cur.R = (int)(b % q.NR);
+    cur.t = (int)(b / q.NR);
+  }
+  cur.oa = q.offsA[cur.iA];
+  cur.ob = q.offsB[cur.iB];
+  Blk nxt = cur, nn = cur;
+  advance(nxt);
+  nxt.oa = q.offsA[nxt.iA < q.cntA ? nxt.iA : 0];
+  nxt.ob = q.offsB[nxt.iB < q.cntB ? nxt.iB : 0];
+  advance(nn);
+  advance(nn);
+  __syncthreads();  // minus-R table staged
+  if (bbeg < bend) {
+    fetch(cur);
     stage();
   }
   __syncthreads();
 
-  for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
-    const Blk k = decode(blk);
+  for (long long blk = bbeg; blk < bend; ++blk) {
+    const Blk k = cur;
     const int t = k.t, R = k.R;
-    const int tm = q.n_tau - 1 - t, mR = q.minusR[R];
-    const int pA = q.pb_off[k.A], pB = q.pb_off[k.B];
-    const bool more = blk + gridDim.x < q.nblocks;
-    if (more) fetch(decode(blk + gridDim.x));
+    const int tm = q.n_tau - 1 - t, mR = mRs[R];
+    const int pA = k.oa.x, pB = k.ob.x;
+    const bool more = blk + 1 < bend;
+    if (more) fetch(nxt);
+    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
+    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
     // Q over unordered pairs (zero outside the live pairs); the pair tables of this
     // thread's entries are held in registers
 #pragma unroll
@@ -237,7 +273,6 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
       }
     }
     __syncthreads();
-    if (more) stage();
 
     CT* Pd = P + ((long long)t * q.NR + R) * slp;
     CT* Pm = P + ((long long)tm * q.NR + mR) * slp;
@@ -247,13 +282,29 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
 #pragma unroll
       for (int Jt = 0; Jt < kJT; ++Jt) acc2[Jt][0] = acc2[Jt][1] = typename M::acc{0, 0, 0, 0};
       // first product for tile tt: rows (p', part) of Q^T against C~_A^T
+      // FP32: all A operands of the tile are read from LDS first, then two independent
+      // accumulation chains (even and odd K steps) keep the matrix pipe fed.  FP64 keeps
+      // one chain with the reads interleaved (its register budget is already full).
       auto gemm1 = [&](int tt) {
-        typename M::acc a1 = {0, 0, 0, 0};
         const int pp = 8 * tt + row_pp;
+        if constexpr (sizeof(RT) == 8) {
+          typename M::acc a1 = {0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < kKA; ++ks)
-          if (ks < nKA) a1 = M::op(Qd[((4 * ks + lk) * kQS + pp) * 2 + row_part], b1[ks], a1);
-        return a1;
+          for (int ks = 0; ks < kKA; ++ks)
+            if (ks < nKA) a1 = M::op(Qd[((4 * ks + lk) * kQS + pp) * 2 + row_part], b1[ks], a1);
+          return a1;
+        }
+        RT av[kKA];
+#pragma unroll
+        for (int ks = 0; ks < kKA; ++ks) av[ks] = ks < nKA ? Qd[((4 * ks + lk) * kQS + pp) * 2 + row_part] : RT(0);
+        __builtin_amdgcn_sched_barrier(0);  // keep every read ahead of the products
+        typename M::acc e = {0, 0, 0, 0}, o = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < kKA; ks += 2) {
+          if (ks < nKA) e = M::op(av[ks], b1[ks], e);
+          if (ks + 1 < nKA) o = M::op(av[ks + 1], b1[ks + 1], o);
+        }
+        return e + o;
       };
       typename M::acc acc1 = gemm1(0);
 #pragma unroll 1
@@ -286,6 +337,12 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
           }
       }
     }
+    if (more) stage();  // Xs, Ys were last read before the barrier above
+    cur = nxt;
+    nxt = nn;
+    nxt.oa = noa;
+    nxt.ob = nob;
+    advance(nn);
     __syncthreads();
   }
 }
@@ -506,31 +563,38 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   float b1[kKJ];
 #pragma unroll
   for (int ks = 0; ks < kKJ; ++ks) b1[ks] = (mm && ks < nKJ) ? CpB[(4 * ks + lk) * q.nppB + 16 * w + li] : 0.f;
+  // Settle these loads here, on every path: otherwise the wait inserted before the first
+  // use of b1 inside the block loop is a full vmcnt(0), which would also wait for the
+  // next block's W prefetch and serialise it with the matrix work.
+  __builtin_amdgcn_s_waitcnt(0);
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
   const int half_a = (q.nA + 1) / 2;
   const int uo = tid >> 1, uh = tid & 1;
+  // Blocks are walked in a contiguous range, so their (tau, R, iA, iB) indices advance by
+  // counting (B fastest) and the atom offsets come from the per-species (pb, orb) tables;
+  // the table entries of block b + 2 are loaded while block b is multiplied.
   struct Blk {
-    int t, R, A, B;
+    int t, R, iA, iB;
+    int2 oa, ob;  // (first product function, first orbital) of atoms A and B
   };
-  auto decode = [&](long long b) {
-    Blk o;
-    const int iB = (int)(b % q.cntB);
-    b /= q.cntB;
-    const int iA = (int)(b % q.cntA);
-    b /= q.cntA;
-    o.R = (int)(b % q.NR);
-    o.t = (int)(b / q.NR);
-    o.A = q.atomsA[iA];
-    o.B = q.atomsB[iB];
-    return o;
+  auto advance = [&](Blk& k) {
+    if (++k.iB == q.cntB) {
+      k.iB = 0;
+      if (++k.iA == q.cntA) {
+        k.iA = 0;
+        if (++k.R == q.NR) {
+          k.R = 0;
+          ++k.t;
+        }
+      }
+    }
   };
   // W rows r = w + 3 u (64 consecutive elements of a row per wavefront), column = lane
   float2 wreg[kW32PF];
   float2 xr;
   const bool lane_ok = lane < q.mB;
   auto fetch = [&](const Blk& k) {
-    const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(q.pb_off[k.A] + w) * q.Np +
-                      q.pb_off[k.B] + lane;
+    const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(k.oa.x + w) * q.Np + k.ob.x + lane;
     const long long step = 3LL * q.Np;
 #pragma unroll
     for (int u = 0; u < kW32PF; ++u) {
@@ -541,8 +605,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   const bool xok = tid < q.nA * q.nB;
   auto fetch_x = [&](const Blk& k) {
     const int a = tid / q.nB, c = tid - a * q.nB;
-    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
-               GR, xok);
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
   };
   auto stash = [&]() {
 #pragma unroll
@@ -576,22 +639,44 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
+  Blk cur;
+  {
+    long long b = bbeg < q.nblocks ? bbeg : 0;
+    cur.iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    cur.iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    cur.R = (int)(b % q.NR);
+    cur.t = (int)(b / q.NR);
+  }
+  auto offsets = [&](Blk& k) {
+    k.oa = q.offsA[k.iA];
+    k.ob = q.offsB[k.iB];
+  };
+  offsets(cur);
+  Blk nxt = cur, nn = cur;
+  advance(nxt);
+  if (bbeg + 1 < bend) offsets(nxt);
+  advance(nn);
+  advance(nn);
   if (bbeg < bend) {
-    const Blk k0 = decode(bbeg);
-    fetch(k0);
-    fetch_x(k0);
+    fetch(cur);
+    fetch_x(cur);
     stash();
   }
   __syncthreads();
   for (long long blk = bbeg; blk < bend; ++blk) {
-    const Blk k = decode(blk);
-    const int oA = q.orb_off[k.A], oB = q.orb_off[k.B];
+    const Blk k = cur;
+    const int oA = k.oa.y, oB = k.ob.y;
     const bool more = blk + 1 < bend;
     if (more) {
-      const Blk kn = decode(blk + 1);
-      fetch(kn);
-      fetch_x(kn);
+      fetch(nxt);
+      fetch_x(nxt);
     }
+    // offsets of block blk + 2 (always loaded, from in-range indices, so that nothing
+    // copies the registers before the end of this block), consumed by the next fetch
+    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
+    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
     f4 acc2[3][2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = f4{0, 0, 0, 0};
@@ -659,6 +744,11 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       const int a = uo / q.nB, bb = uo - a * q.nB;
       S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
     }
+    cur = nxt;
+    nxt = nn;
+    nxt.oa = noa;
+    nxt.ob = nob;
+    advance(nn);
     __syncthreads();
   }
 }
@@ -676,6 +766,8 @@ PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, i
   q.mpA = A.m_pad;
   q.mpB = B.m_pad;
   q.atomsA = A.atoms_dev;
+  q.offsA = A.offs_dev;
+  q.offsB = B.offs_dev;
   q.cntA = (int)A.atoms.size();
   q.atomsB = B.atoms_dev;
   q.cntB = (int)B.atoms.size();
@@ -703,12 +795,28 @@ void launch_p_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
                         double g, gw_precision p, hipStream_t s) {
   const PairArgs q = make_args(c, A, B, (c->n_tau + 1) / 2);
   if (q.nblocks == 0) return;
-  if (p == GW_FP64)
-    hipLaunchKernelGGL((p_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(256), 0, s,
-                       (const double2*)GR, (double2*)P, A.Cpair, B.Cpair, q, g);
-  else
-    hipLaunchKernelGGL((p_mfma<float, float2>), dim3(grid_for(q.nblocks)), dim3(256), 0, s, (const float2*)GR,
-                       (float2*)P, A.Cpair32, B.Cpair32, q, g);
+  const int sh = (A.np_pad == 48 && B.np_pad == 48 && A.m_pad == 64 && (B.m + 15) / 16 == 4)   ? 1
+                 : (A.np_pad == 16 && B.np_pad == 16 && A.m_pad == 16 && (B.m + 15) / 16 == 1) ? 2
+                                                                                              : 0;
+  const dim3 grid(grid_for(q.nblocks)), block(256);
+#define GWR_P(RT, CT, SHV, CA, CB)                                                                  \
+  hipLaunchKernelGGL((p_mfma<RT, CT, SHV>), grid, block, 0, s, (const CT*)GR, (CT*)P, CA, CB, q, g)
+  if (p == GW_FP64) {
+    if (sh == 1)
+      GWR_P(double, double2, 1, A.Cpair, B.Cpair);
+    else if (sh == 2)
+      GWR_P(double, double2, 2, A.Cpair, B.Cpair);
+    else
+      GWR_P(double, double2, 0, A.Cpair, B.Cpair);
+  } else {
+    if (sh == 1)
+      GWR_P(float, float2, 1, A.Cpair32, B.Cpair32);
+    else if (sh == 2)
+      GWR_P(float, float2, 2, A.Cpair32, B.Cpair32);
+    else
+      GWR_P(float, float2, 0, A.Cpair32, B.Cpair32);
+  }
+#undef GWR_P
 }
 
 void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,

@@ -28,6 +28,7 @@ struct SpeciesDev {
   float* Cpair32 = nullptr;     // same, FP32
   std::vector<int> atoms;       // atoms of this species (host)
   int* atoms_dev = nullptr;     // same on device
+  int2* offs_dev = nullptr;     // per atom of this species: (first product function, first orbital)
 };
 
 struct PairTables {

@@ -7,10 +7,11 @@ A step is the whole path on one synthetic cell with inputs resident in HBM:
     G(k,tau) -k2r-> G(R,tau) -> P (Eq. 5) and Sigma (Eq. 8, with W(R,tau))
     -> drain (R->k, tau->Matsubara) of P and of Sigma -> electron count.
 The metric is the algorithmic P + Sigma GFLOP/s of the whole step.  The default
-(mixed) path stores G, W, P as complex64 and runs the contractions on the FP32
-matrix cores; the lattice and Matsubara transforms, the Sigma orbital sums and
-the electron count are FP64.  The plain FP64 path is timed after it for the
-speedup.  One JSON line is printed with a roofline entry for the dominant kernel
+(mixed) path stores G, W, P as complex64 and runs the contractions on the matrix
+cores with split-precision BF16 products where a kernel exists (Sigma) and FP32
+otherwise (P); the lattice and Matsubara transforms, the Sigma orbital sums and
+the electron count are FP64.  The FP32 and the plain FP64 paths are timed after it
+on the same inputs, each with its error on the oracle's sample.  One JSON line is printed with a roofline entry for the dominant kernel
 (timed with events on the launch stream) and the CPU oracle timed on a bounded
 sample, whose outputs also give the error of the timed path.
 """
@@ -162,17 +163,10 @@ def kernel_roofs(spec, prec, fp, fs):
     return roofs
 
 
-def cpu_baseline(spec, d, fp, fs, log, g, cell, prec):
+def oracle_sample(spec, d, log):
     """The FP64 oracle on a bounded sample: P^q(tau) for one (tau, q) and Sigma^k(tau) for one
-    (tau, k) of the same cell; scaled to the metric as (fraction of the step's work) / time.
-    The same slices of the timed GPU path (recomputed, then R -> k) give its error."""
-    import torch
+    (tau, k) of the same cell.  Returns the slices and the CPU seconds spent on each."""
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
     t, q = spec.n_tau // 3, 1
     t0 = time.perf_counter()
     Pq = oracle.polarizability_q(d["Gk_h"], spec, d["C"], spec.spin, taus=[t], qs=[q])[0, 0]
@@ -181,27 +175,43 @@ def cpu_baseline(spec, d, fp, fs, log, g, cell, prec):
     t0 = time.perf_counter()
     Sk = oracle.self_energy_k(d["Gk_h"], WR, spec, d["C"], taus=[t], ks=[q])[0, 0]
     ts = time.perf_counter() - t0
-    frac = 1.0 / (spec.n_tau * spec.N_R)  # one (tau, q) slice of the whole P (and of Sigma)
-    work = frac * (fp + fs) * spec.n_tau * spec.N_R
     log(f"cpu oracle sample: P {tp:.1f}s, Sigma {ts:.1f}s")
-    # the timed path's outputs on the same slices
+    return dict(t=t, q=q, P=Pq, S=Sk, tp=tp, ts=ts)
+
+
+def slice_error(g, cell, d, spec, prec, smp, log):
+    """Error of the timed path on the oracle's slices (recomputed, then R -> k)."""
+    import torch
     g.gw_fourier_k2r(cell, d["Gk"], d["GR"], basis=0)
     g.gw_polarizability(cell, d["GR"], d["P"], spec.spin, prec=prec)
     g.gw_self_energy(cell, d["GR"], d["W"], d["S"], prec=prec)
     g.gw_fourier_r2k(cell, d["P"], d["P"], basis=1)
     g.gw_fourier_r2k(cell, d["S"], d["S"], basis=0)
     torch.cuda.synchronize()
+    t, q = smp["t"], smp["q"]
     Pg = d["P"][t, q].cpu().numpy().astype(np.complex128)
     Sg = d["S"][t, q].cpu().numpy()
     err = {}
-    for name, a, b in (("P", Pg, Pq), ("Sigma", Sg, Sk)):
+    for name, a, b in (("P", Pg, smp["P"]), ("Sigma", Sg, smp["S"])):
         mx = float(np.max(np.abs(a - b)))
         err[name] = {"max_abs": mx, "rel": mx / float(np.max(np.abs(b)))}
-    log(f"error vs oracle on the sampled slices: {err}")
-    return ({"value": work / (tp + ts) / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
-             "sample": f"k-space FP64 oracle: P^q(tau) for 1 tau x 1 q and Sigma^k(tau) for 1 tau x 1 k of "
-                       f"the {spec.n_atoms}-atom cell (each a 1/{spec.n_tau * spec.N_R} share of the step's "
-                       f"P or Sigma output); {tp + ts:.1f} s"}, err)
+    log(f"{prec}: error vs oracle on the sampled slices: {err}")
+    return err
+
+
+def cpu_baseline(spec, smp, fp, fs):
+    """The oracle's sample as a rate: (its share of the step's algorithmic work) / CPU time."""
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    work = (fp + fs)  # one (tau, q) slice of P and of Sigma: 1 / (n_tau N_R) of the step each
+    secs = smp["tp"] + smp["ts"]
+    return {"value": work / secs / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"k-space FP64 oracle: P^q(tau) for 1 tau x 1 q and Sigma^k(tau) for 1 tau x 1 k of "
+                      f"the {spec.n_atoms}-atom cell (each a 1/{spec.n_tau * spec.N_R} share of the step's "
+                      f"P or Sigma output); {secs:.1f} s"}
 
 
 def time_path(g, spec, prec, steps, warmup, torch, log):
@@ -292,8 +302,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"],
-                    help="contraction arithmetic: fp32 = the mixed path (default), fp64 = plain FP64")
+    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
+                    help="contraction arithmetic: bf16x3 = the mixed path of the 72-atom workload (split-precision "
+                         "BF16 products, complex64 storage, FP64 transforms and sums; default), fp32 = FP32 "
+                         "matrix cores, fp64 = plain FP64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the step benchmark")
@@ -353,17 +365,26 @@ def main():
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / scale, "peak": peak / scale,
                      "unit": unit, "frac": achieved / peak, "traffic": traffic_for(dom, args.prec)},
     }
+    smp = None
     if not args.no_cpu:
-        out["cpu_baseline"], out["config"]["error_vs_oracle"] = cpu_baseline(spec, d, fp, fs, log, g, cell,
-                                                                             args.prec)
-    if args.prec != "fp64" and not args.no_fp64:
-        del d, cell
+        smp = oracle_sample(spec, d, log)
+        out["cpu_baseline"] = cpu_baseline(spec, smp, fp, fs)
+        out["config"]["error_vs_oracle"] = slice_error(g, cell, d, spec, args.prec, smp, log)
+    del d, cell
+    torch.cuda.empty_cache()
+    # the other mixed-precision path, then the plain FP64 path, on the same inputs
+    others = [] if args.no_fp64 else [x for x in ("fp32", "bf16x3") if x != args.prec] + ["fp64"]
+    if args.prec == "fp64":
+        others = []
+    for alt in others:
+        da, cella, msa, pera = time_path(g, spec, alt, max(1, min(args.steps, 3)), 1, torch, log)
+        out["config"][f"{alt}_ms_per_step"] = msa
+        out["config"][f"{alt}_per_kernel_ms"] = pera
+        out["config"][f"speedup_vs_{alt}"] = msa / ms
+        if smp is not None:
+            out["config"][f"{alt}_error_vs_oracle"] = slice_error(g, cella, da, spec, alt, smp, log)
+        del da, cella
         torch.cuda.empty_cache()
-        d64, cell64, ms64, per64 = time_path(g, spec, "fp64", max(1, min(args.steps, 3)), 1, torch, log)
-        out["config"]["fp64_ms_per_step"] = ms64
-        out["config"]["fp64_per_kernel_ms"] = per64
-        out["config"]["speedup_vs_fp64"] = ms64 / ms
-        del d64, cell64
     print(json.dumps(out), flush=True)
 
 

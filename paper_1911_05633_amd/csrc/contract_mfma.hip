@@ -753,6 +753,264 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   }
 }
 
+// ---------------------------------------------------------------------------
+// self-energy on the BF16 matrix cores with split-precision products (GW_BF16X3).
+// Every FP32 operand x is split as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi),
+// and a product a b is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo lo term, of
+// relative size 2^-16, is dropped), accumulated in FP32 by v_mfma_f32_16x16x32_bf16.
+// Same blocks, walk, prefetch and FP64 unfold as s_mfma32; the W block is split once
+// when it is staged and sits in LDS as four bf16 planes (re hi, re lo, im hi, im lo;
+// row stride 72: the 16-byte A-operand reads of eight lanes hit distinct banks).
+// GEMM1 (Z = W C~_B) takes K = 64 in two 32-deep steps.  GEMM2 (K = C~_A^T Z) takes
+// its K = 64 product functions I in two steps of two I tiles: the D fragments of GEMM1
+// for tiles 2s and 2s + 1 (rows 4 g + j in register j of lane group g) are split in
+// registers and form the B operand with K slot 8 g + e <-> I = 16 (2 s + e / 4) + 4 g + e % 4;
+// C~_A is stored in LDS in that slot order.  Shapes: 9-orbital species with
+// 49..64 product functions on both atoms.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int kWBS = 72;                    // bf16 row stride of a W plane
+constexpr int kWBP = kMP * kWBS;            // bf16 elements per W plane
+constexpr int kCBS = 40;                    // bf16 per (plane, step, p) row of C~_A: 4 groups of 8 + pad
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3(
+    const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
+    const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
+  __shared__ __align__(16) __bf16 Wp[4 * kWBP];           // W planes, then the K block (FP32)
+  __shared__ __align__(16) __bf16 Cap[2 * 2 * kPL * kCBS];  // C~_A [hi|lo][step][p][slot]
+  __shared__ float2 Xs[81];
+  float2* Ks = reinterpret_cast<float2*>(Wp);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const bool mm = 16 * w < q.nppB;
+  // C~_A in GEMM2 slot order, split
+  for (int i = tid; i < 2 * kPL * 32; i += kS32Threads) {
+    const int st = i / (kPL * 32), r = i - st * kPL * 32, p = r / 32, slot = r - p * 32;
+    const int g = slot >> 3, e = slot & 7;
+    const int I = 16 * (2 * st + (e >> 2)) + 4 * g + (e & 3);
+    const float v = (I < q.mpA && p < q.nppA) ? CpA[I * q.nppA + p] : 0.f;
+    __bf16 h, l;
+    split_bf16(v, h, l);
+    Cap[((0 * 2 + st) * kPL + p) * kCBS + 8 * g + e] = h;
+    Cap[((1 * 2 + st) * kPL + p) * kCBS + 8 * g + e] = l;
+  }
+  // C~_B operands of GEMM1: lane (p' = 16 w + li, g) holds J = 32 s + 8 g + e
+  bf8 cbh[2], cbl[2];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int J = 32 * st + 8 * lk + e;
+      const float v = mm ? CpB[J * q.nppB + 16 * w + li] : 0.f;
+      __bf16 h, l;
+      split_bf16(v, h, l);
+      cbh[st][e] = h;
+      cbl[st][e] = l;
+    }
+  __builtin_amdgcn_s_waitcnt(0);
+  const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+  const int half_a = (q.nA + 1) / 2;
+  const int uo = tid >> 1, uh = tid & 1;
+  struct Blk {
+    int t, R, iA, iB;
+    int2 oa, ob;
+  };
+  auto advance = [&](Blk& k) {
+    if (++k.iB == q.cntB) {
+      k.iB = 0;
+      if (++k.iA == q.cntA) {
+        k.iA = 0;
+        if (++k.R == q.NR) {
+          k.R = 0;
+          ++k.t;
+        }
+      }
+    }
+  };
+  float2 wreg[kW32PF];
+  float2 xr;
+  const bool lane_ok = lane < q.mB;
+  auto fetch = [&](const Blk& k) {
+    const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(k.oa.x + w) * q.Np + k.ob.x + lane;
+    const long long step = 3LL * q.Np;
+#pragma unroll
+    for (int u = 0; u < kW32PF; ++u) {
+      wreg[u] = ldraw(p, WR, lane_ok && w + 3 * u < q.mA);
+      p += step;
+    }
+  };
+  const bool xok = tid < q.nA * q.nB;
+  auto fetch_x = [&](const Blk& k) {
+    const int a = tid / q.nB, c = tid - a * q.nB;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < kW32PF; ++u) {
+      const int r = w + 3 * u;
+      if (r < kMP) {
+        const float2 v = keep(wreg[u], r < q.mA && lane_ok);
+        __bf16 h, l;
+        split_bf16(v.x, h, l);
+        Wp[0 * kWBP + r * kWBS + lane] = h;
+        Wp[1 * kWBP + r * kWBS + lane] = l;
+        split_bf16(v.y, h, l);
+        Wp[2 * kWBP + r * kWBS + lane] = h;
+        Wp[3 * kWBP + r * kWBS + lane] = l;
+      }
+    }
+    if (xok) Xs[tid] = xr;
+  };
+  // GEMM1 for I tile it: zr / zi = rows 16 it .. 16 it + 15 of Re / Im (W C~_B)
+  auto gemm1 = [&](int it, f4& zr, f4& zi) {
+    zr = f4{0, 0, 0, 0};
+    zi = f4{0, 0, 0, 0};
+    const int row = (16 * it + li) * kWBS + 8 * lk;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      bf8 a[4];
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[pl] = *reinterpret_cast<const bf8*>(&Wp[pl * kWBP + row + 32 * st]);
+      zr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], cbh[st], zr, 0, 0, 0);
+      zi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], cbh[st], zi, 0, 0, 0);
+      zr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], cbl[st], zr, 0, 0, 0);
+      zi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], cbl[st], zi, 0, 0, 0);
+      zr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], cbh[st], zr, 0, 0, 0);
+      zi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[3], cbh[st], zi, 0, 0, 0);
+    }
+  };
+  // GEMM2 step st: acc2[m][part] += C~_A^T Z over I tiles 2 st, 2 st + 1
+  auto gemm2 = [&](int st, const f4& zr0, const f4& zi0, const f4& zr1, const f4& zi1, f4 (&acc2)[3][2]) {
+    bf8 brh, brl, bih, bil;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      __bf16 h, l;
+      split_bf16(zr0[e], h, l);
+      brh[e] = h;
+      brl[e] = l;
+      split_bf16(zr1[e], h, l);
+      brh[4 + e] = h;
+      brl[4 + e] = l;
+      split_bf16(zi0[e], h, l);
+      bih[e] = h;
+      bil[e] = l;
+      split_bf16(zi1[e], h, l);
+      bih[4 + e] = h;
+      bil[4 + e] = l;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const bf8 ah = *reinterpret_cast<const bf8*>(&Cap[((0 * 2 + st) * kPL + 16 * m + li) * kCBS + 8 * lk]);
+      const bf8 al = *reinterpret_cast<const bf8*>(&Cap[((1 * 2 + st) * kPL + 16 * m + li) * kCBS + 8 * lk]);
+      acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brh, acc2[m][0], 0, 0, 0);
+      acc2[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bih, acc2[m][1], 0, 0, 0);
+      acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brl, acc2[m][0], 0, 0, 0);
+      acc2[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bil, acc2[m][1], 0, 0, 0);
+      acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, brh, acc2[m][0], 0, 0, 0);
+      acc2[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bih, acc2[m][1], 0, 0, 0);
+    }
+  };
+
+  const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
+  const long long bbeg = (long long)blockIdx.x * per;
+  const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
+  Blk cur;
+  {
+    long long b = bbeg < q.nblocks ? bbeg : 0;
+    cur.iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    cur.iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    cur.R = (int)(b % q.NR);
+    cur.t = (int)(b / q.NR);
+  }
+  cur.oa = q.offsA[cur.iA];
+  cur.ob = q.offsB[cur.iB];
+  Blk nxt = cur, nn = cur;
+  advance(nxt);
+  nxt.oa = q.offsA[nxt.iA < q.cntA ? nxt.iA : 0];
+  nxt.ob = q.offsB[nxt.iB < q.cntB ? nxt.iB : 0];
+  advance(nn);
+  advance(nn);
+  if (bbeg < bend) {
+    fetch(cur);
+    fetch_x(cur);
+    stash();
+  }
+  __syncthreads();
+  for (long long blk = bbeg; blk < bend; ++blk) {
+    const Blk k = cur;
+    const int oA = k.oa.y, oB = k.ob.y;
+    const bool more = blk + 1 < bend;
+    if (more) {
+      fetch(nxt);
+      fetch_x(nxt);
+    }
+    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
+    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
+    f4 acc2[3][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = f4{0, 0, 0, 0};
+    if (mm) {
+      f4 zr0, zi0, zr1, zi1;
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        gemm1(2 * st, zr0, zi0);
+        gemm1(2 * st + 1, zr1, zi1);
+        gemm2(st, zr0, zi0, zr1, zi1, acc2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    __syncthreads();  // every wavefront is done with W
+    if (mm) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          Ks[(16 * m + 4 * lk + j) * kKS + 16 * w + li] = make_float2(acc2[m][0][j], acc2[m][1][j]);
+    }
+    __syncthreads();
+    double sr = 0, si = 0;
+    const bool live = uo < q.nA * q.nB;
+    if (live) {
+      const int a = uo / q.nB, bb = uo - a * q.nB;
+      const int a0 = uh ? half_a : 0, a1 = uh ? q.nA : half_a;
+      int pb[9];
+#pragma unroll
+      for (int bp = 0; bp < 9; ++bp) pb[bp] = bp < q.nB ? pair_index(bb, bp, q.nB) : 0;
+      for (int ap = a0; ap < a1; ++ap) {
+        const float2* Kr = Ks + pair_index(a, ap, q.nA) * kKS;
+        const float2* Xr = Xs + ap * q.nB;
+#pragma unroll
+        for (int bp = 0; bp < 9; ++bp)
+          if (bp < q.nB) {
+            const float2 kv = Kr[pb[bp]], x = Xr[bp];
+            sr += (double)kv.x * x.x - (double)kv.y * x.y;
+            si += (double)kv.x * x.y + (double)kv.y * x.x;
+          }
+      }
+    }
+    sr += __shfl_xor(sr, 1);
+    si += __shfl_xor(si, 1);
+    __syncthreads();  // K and X no longer read
+    if (more) stash();
+    if (live && uh == 0) {
+      const int a = uo / q.nB, bb = uo - a * q.nB;
+      S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
+    }
+    cur = nxt;
+    nxt = nn;
+    nxt.oa = noa;
+    nxt.ob = nob;
+    advance(nn);
+    __syncthreads();
+  }
+}
+
 PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, int n_half) {
   PairArgs q;
   q.nA = A.n;
@@ -830,6 +1088,9 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);
+  else if (p == GW_BF16X3 && A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)
+    hipLaunchKernelGGL(s_bf16x3, dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR, (const float2*)WR,
+                       (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)  // n = 9 with m in (48, 64]: the Si-like species
     hipLaunchKernelGGL((s_mfma32<4, 16, 3>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
                        (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);

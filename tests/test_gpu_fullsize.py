@@ -48,7 +48,7 @@ def _err(pairs_of_arrays):
     return num / den
 
 
-@pytest.mark.parametrize("cfg,prec", [(3, "fp32"), (3, "fp64"), (4, "fp32"), (4, "fp64")])
+@pytest.mark.parametrize("cfg,prec", [(3, "fp32"), (3, "bf16x3"), (3, "fp64"), (4, "fp32"), (4, "fp64")])
 def test_full_size_path_sampled(cfg, prec):
     import torch
     import paper_1911_05633_amd as g
@@ -56,7 +56,7 @@ def test_full_size_path_sampled(cfg, prec):
     print(f"[full size] config {cfg} ({spec.name}) {prec}", flush=True)
     Gk_h, C, A, sR, et = _inputs(spec)
     nt, NR, No, Np = spec.n_tau, spec.N_R, spec.N_orb, spec.N_pb
-    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64  # bf16x3 stores complex64 too
     cell = g.Cell.from_spec(spec, C)
     Gk = torch.from_numpy(Gk_h).cuda()
     GR = torch.empty(Gk.shape, dtype=cdt, device="cuda")

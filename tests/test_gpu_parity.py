@@ -289,3 +289,23 @@ def test_chained_path_mixed(name):
     print(f"mixed-path error: P {eP:.2e}, Sigma {eS:.2e}", flush=True)
     assert eP < 1e-5 and eS < 1e-5
     assert abs(float(host(n)[0]) - oracle.electron_count(d["GR"][-1, 0], spec.spin)) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["si8", "two_species"])
+def test_bf16x3_paths(name):
+    """GW_BF16X3: split-precision BF16 products in Sigma (9-orbital species), FP32 kernels
+    elsewhere; complex64 storage; bar 1e-5 relative against the FP64 oracle."""
+    import torch
+    import paper_1911_05633_amd as g
+    d = case(name)
+    spec = d["spec"]
+    cell = gpu_cell(d)
+    GR = dev(d["GR"], torch.complex64)
+    P = torch.zeros((spec.n_tau, spec.N_R, spec.N_pb, spec.N_pb), dtype=torch.complex64, device="cuda")
+    g.gw_polarizability(cell, GR, P, spec.spin, prec="bf16x3")
+    S = torch.zeros((spec.n_tau, spec.N_R, spec.N_orb, spec.N_orb), dtype=torch.complex128, device="cuda")
+    g.gw_self_energy(cell, GR, dev(d["WR"], torch.complex64), S, prec="bf16x3")
+    eP = relmax(host(P)[d["taus"]].astype(np.complex128), d["PR"])
+    eS = relmax(host(S)[d["taus"]], d["SR"])
+    print(f"[bf16x3] {name}: P {eP:.2e}, Sigma {eS:.2e}", flush=True)
+    assert eP < 1e-5 and eS < 1e-5

@@ -7,9 +7,8 @@ A step is the whole path on one synthetic cell with inputs resident in HBM:
     G(k,tau) -k2r-> G(R,tau) -> P (Eq. 5) and Sigma (Eq. 8, with W(R,tau))
     -> drain (R->k, tau->Matsubara) of P and of Sigma -> electron count.
 The metric is the algorithmic P + Sigma GFLOP/s of the whole step.  The default
-(mixed) path stores G, W, P as complex64 and runs the contractions on the matrix
-cores with split-precision BF16 products where a kernel exists (Sigma) and FP32
-otherwise (P); the lattice and Matsubara transforms, the Sigma orbital sums and
+(mixed) path stores G, W, P as complex64 and runs both contractions on the BF16
+matrix cores with split-precision (hi + lo) products and FP32 accumulation; the lattice and Matsubara transforms, the Sigma orbital sums and
 the electron count are FP64.  The FP32 and the plain FP64 paths are timed after it
 on the same inputs, each with its error on the oracle's sample.  One JSON line is printed with a roofline entry for the dominant kernel
 (timed with events on the launch stream) and the CPU oracle timed on a bounded

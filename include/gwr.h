@@ -58,12 +58,11 @@ typedef enum {
  *   GW_FP64   : G, W, P are complex128; FP64 MFMA; Sigma complex128.
  *   GW_FP32   : G, W, P are complex64; FP32 MFMA, FP32 accumulation;
  *               Sigma is accumulated over atom-orbital sums in FP64 and stored complex128.
- *   GW_BF16X3 : storage as GW_FP32; in Sigma's contractions each FP32 operand is split into
+ *   GW_BF16X3 : storage as GW_FP32; in both contractions each FP32 operand is split into
  *               bf16 hi + lo and the products hi*hi + hi*lo + lo*hi run on the BF16 matrix
- *               cores with FP32 accumulation (relative error a few 1e-6; the FP64 orbital
- *               sums as for GW_FP32).  Block shapes without such a kernel (species other
- *               than 9 orbitals with 49..64 product functions) and the polarizability run
- *               the FP32 kernels. */
+ *               cores with FP32 accumulation (relative error a few 1e-6; Sigma's FP64
+ *               orbital sums as for GW_FP32).  Block shapes without such a kernel (species
+ *               other than 9 orbitals with 49..64 product functions) run the FP32 kernels. */
 typedef enum { GW_FP64 = 0, GW_FP32 = 1, GW_BF16X3 = 2 } gw_precision;
 
 /* Storage type of a transform operand.  Transforms always compute in FP64. */

@@ -347,6 +347,257 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   }
 }
 
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int kWBS = 72;                    // bf16 row stride of a W plane
+constexpr int kWBP = kMP * kWBS;            // bf16 elements per W plane
+constexpr int kCBS = 40;                    // bf16 per (plane, step, p) row of C~_A: 4 groups of 8 + pad
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// ---------------------------------------------------------------------------
+// polarizability on the BF16 matrix cores with split-precision products (GW_BF16X3),
+// for 9-orbital species with 49..64 product functions on both atoms.  Same blocks, walk,
+// G-tile prefetch and tau mirror as p_mfma.  Q is formed in FP32 and written split into
+// bf16 hi / lo planes stored transposed, Q^T[p'][p] (row stride 72: the 16-byte A-operand
+// reads of eight lanes hit distinct banks).  GEMM1 (wavefront w, I tile w):
+// D1[p'][I] = sum_p Q[p][p'] C~_A[I][p] per part and per 16-row block pb of p', K = p in
+// two 32-deep steps (p >= 48 zero).  GEMM2: acc[J][I] += sum_p' C~_B[J][p'] D1[p'][I], its
+// K = p' taken in steps of two D1 blocks split in registers, K slot 8 g + e <->
+// p' = 32 s + 16 (e / 4) + 4 g + e % 4; C~_B sits in LDS in that slot order.
+// ---------------------------------------------------------------------------
+constexpr int kQBS = 72;              // bf16 row stride of a Q^T plane
+constexpr int kQBP = kPL * kQBS;      // bf16 elements per plane
+constexpr int kCBB = 40;              // bf16 per (plane, step, J) row of C~_B
+
+__global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR, float2* __restrict__ P,
+                                                   const float* __restrict__ CpA, const float* __restrict__ CpB,
+                                                   const PairArgs q, double g) {
+  __shared__ float2 Xs[kMaxOrb * kMaxOrb], Ys[kMaxOrb * kMaxOrb];
+  __shared__ __align__(16) __bf16 Qb[4 * kQBP];                // [part][hi|lo][p'][p]
+  __shared__ __align__(16) __bf16 Cbb[2 * 2 * kMP * kCBB];     // [hi|lo][step][J][slot]
+  __shared__ unsigned char ta[kPL], tb[kPL], tc[kPL], td[kPL];
+  __shared__ int mRs[kMaxR];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  if (tid < q.npA) pair_of(tid, q.nA, ta[tid], tb[tid]);
+  if (tid < q.npB) pair_of(tid, q.nB, tc[tid], td[tid]);
+  for (int i = tid; i < q.NR; i += 256) mRs[i] = q.minusR[i];
+  for (int i = tid; i < 4 * kQBP; i += 256) Qb[i] = (__bf16)0.f;  // p >= 48 stays zero
+  for (int i = tid; i < 2 * kMP * 32; i += 256) {
+    const int st = i / (kMP * 32), r = i - st * kMP * 32, J = r / 32, slot = r - J * 32;
+    const int gg = slot >> 3, e = slot & 7;
+    const int pp = 32 * st + 16 * (e >> 2) + 4 * gg + (e & 3);
+    const float v = (J < q.mpB && pp < q.nppB) ? CpB[J * q.nppB + pp] : 0.f;
+    __bf16 h, l;
+    split_bf16(v, h, l);
+    Cbb[((0 * 2 + st) * kMP + J) * kCBB + 8 * gg + e] = h;
+    Cbb[((1 * 2 + st) * kMP + J) * kCBB + 8 * gg + e] = l;
+  }
+  // GEMM1 B operand: lane (I = 16 w + li, g) holds p = 32 s + 8 g + e
+  bf8 cah[2], cal[2];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int pp = 32 * st + 8 * lk + e;
+      const float v = pp < q.nppA ? CpA[(16 * w + li) * q.nppA + pp] : 0.f;
+      __bf16 h, l;
+      split_bf16(v, h, l);
+      cah[st][e] = h;
+      cal[st][e] = l;
+    }
+  __syncthreads();  // pair tables, minus-R table, Q zero padding staged
+  // per-thread Q entries (p fastest): packed (a, b, c, d) of p = {a, b}, p' = {c, d}
+  unsigned qpk[kQE];
+  int qoff[kQE];
+#pragma unroll
+  for (int e = 0; e < kQE; ++e) {
+    const int i = tid + 256 * e;
+    const int pp = i / q.nppA, p = i - pp * q.nppA;
+    qoff[e] = pp * kQBS + p;
+    qpk[e] = (i < q.nppA * q.nppB && p < q.npA && pp < q.npB)
+                 ? (unsigned)ta[p] | ((unsigned)tb[p] << 8) | ((unsigned)tc[pp] << 16) | ((unsigned)td[pp] << 24)
+                 : 0xffffffffu;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+  struct Blk {
+    int t, R, iA, iB;
+    int2 oa, ob;
+  };
+  auto advance = [&](Blk& k) {
+    if (++k.iB == q.cntB) {
+      k.iB = 0;
+      if (++k.iA == q.cntA) {
+        k.iA = 0;
+        if (++k.R == q.NR) {
+          k.R = 0;
+          ++k.t;
+        }
+      }
+    }
+  };
+  float2 xr, yr;
+  const bool xok = tid < q.nA * q.nB;
+  auto fetch = [&](const Blk& k) {
+    const int a = tid / q.nB, c = tid - a * q.nB;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
+    const int d = tid / q.nA, bb = tid - d * q.nA;
+    yr = ldraw(GR + ((long long)(q.n_tau - 1 - k.t) * q.NR + mRs[k.R]) * sl + (long long)(k.ob.y + d) * q.No +
+                   k.oa.y + bb,
+               GR, xok);
+  };
+  auto stage = [&]() {
+    if (xok) {
+      Xs[tid] = xr;
+      Ys[tid] = yr;
+    }
+  };
+  const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
+  const long long bbeg = (long long)blockIdx.x * per;
+  const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
+  Blk cur;
+  {
+    long long b = bbeg < q.nblocks ? bbeg : 0;
+    cur.iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    cur.iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    cur.R = (int)(b % q.NR);
+    cur.t = (int)(b / q.NR);
+  }
+  cur.oa = q.offsA[cur.iA];
+  cur.ob = q.offsB[cur.iB];
+  Blk nxt = cur, nn = cur;
+  advance(nxt);
+  nxt.oa = q.offsA[nxt.iA < q.cntA ? nxt.iA : 0];
+  nxt.ob = q.offsB[nxt.iB < q.cntB ? nxt.iB : 0];
+  advance(nn);
+  advance(nn);
+  if (bbeg < bend) {
+    fetch(cur);
+    stage();
+  }
+  __syncthreads();
+  // GEMM1 for part pt and p' block pb
+  auto gemm1 = [&](int pt, int pb) {
+    f4 d = {0, 0, 0, 0};
+    const int row = (16 * pb + li) * kQBS + 8 * lk;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const bf8 ah = *reinterpret_cast<const bf8*>(&Qb[(2 * pt + 0) * kQBP + row + 32 * st]);
+      const bf8 al = *reinterpret_cast<const bf8*>(&Qb[(2 * pt + 1) * kQBP + row + 32 * st]);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, cah[st], d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, cal[st], d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, cah[st], d, 0, 0, 0);
+    }
+    return d;
+  };
+  for (long long blk = bbeg; blk < bend; ++blk) {
+    const Blk k = cur;
+    const int t = k.t, R = k.R;
+    const int tm = q.n_tau - 1 - t, mR = mRs[R];
+    const int pA = k.oa.x, pB = k.ob.x;
+    const bool more = blk + 1 < bend;
+    if (more) fetch(nxt);
+    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
+    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
+    // Q over unordered pairs, written split and transposed
+#pragma unroll
+    for (int e = 0; e < kQE; ++e) {
+      const int i = tid + 256 * e;
+      if (i < q.nppA * q.nppB) {
+        float qr = 0, qi = 0;
+        const unsigned pk = qpk[e];
+        if (pk != 0xffffffffu) {
+          const int a = pk & 0xff, bq = (pk >> 8) & 0xff, c = (pk >> 16) & 0xff, d = pk >> 24;
+          const int nB = q.nB, nA = q.nA;
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int c1 = s2 ? d : c, d1 = s2 ? c : d;
+            if (s2 == 1 && c == d) break;
+            float2 x = Xs[a * nB + c1], y = Ys[d1 * nA + bq];
+            qr += x.x * y.x - x.y * y.y;
+            qi += x.x * y.y + x.y * y.x;
+            if (a != bq) {
+              x = Xs[bq * nB + c1];
+              y = Ys[d1 * nA + a];
+              qr += x.x * y.x - x.y * y.y;
+              qi += x.x * y.y + x.y * y.x;
+            }
+          }
+        }
+        __bf16 h, l;
+        split_bf16(qr, h, l);
+        Qb[0 * kQBP + qoff[e]] = h;
+        Qb[1 * kQBP + qoff[e]] = l;
+        split_bf16(qi, h, l);
+        Qb[2 * kQBP + qoff[e]] = h;
+        Qb[3 * kQBP + qoff[e]] = l;
+      }
+    }
+    __syncthreads();
+
+    float2* Pd = P + ((long long)t * q.NR + R) * slp;
+    float2* Pm = P + ((long long)tm * q.NR + mR) * slp;
+    {
+      f4 acc2[4][2];
+#pragma unroll
+      for (int Jt = 0; Jt < 4; ++Jt) acc2[Jt][0] = acc2[Jt][1] = f4{0, 0, 0, 0};
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt) {
+          const f4 d0 = gemm1(pt, 2 * st);
+          const f4 d1 = st == 0 ? gemm1(pt, 1) : f4{0, 0, 0, 0};
+          bf8 bh, bl;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            __bf16 h, l;
+            split_bf16(d0[e], h, l);
+            bh[e] = h;
+            bl[e] = l;
+            split_bf16(d1[e], h, l);
+            bh[4 + e] = h;
+            bl[4 + e] = l;
+          }
+#pragma unroll
+          for (int Jt = 0; Jt < 4; ++Jt) {
+            const bf8 ah = *reinterpret_cast<const bf8*>(&Cbb[((0 * 2 + st) * kMP + 16 * Jt + li) * kCBB + 8 * lk]);
+            const bf8 al = *reinterpret_cast<const bf8*>(&Cbb[((1 * 2 + st) * kMP + 16 * Jt + li) * kCBB + 8 * lk]);
+            acc2[Jt][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc2[Jt][pt], 0, 0, 0);
+            acc2[Jt][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc2[Jt][pt], 0, 0, 0);
+            acc2[Jt][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc2[Jt][pt], 0, 0, 0);
+          }
+        }
+      }
+      const int I = 16 * w + li;
+      if (I < q.mA) {
+#pragma unroll
+        for (int Jt = 0; Jt < 4; ++Jt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int J = 16 * Jt + 4 * lk + j;
+            if (J < q.mB) {
+              const double re = -g * (double)acc2[Jt][0][j], im = -g * (double)acc2[Jt][1][j];
+              stc(Pd + (long long)(pA + I) * q.Np + pB + J, re, im);
+              if (t != tm) stc(Pm + (long long)(pB + J) * q.Np + pA + I, re, im);
+            }
+          }
+      }
+    }
+    if (more) stage();
+    cur = nxt;
+    nxt = nn;
+    nxt.oa = noa;
+    nxt.ob = nob;
+    advance(nn);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // self-energy.  192 threads: wavefront w owns the 16 pairs p' = 16 w .. 16 w + 15 of
 // atom B (idle in the matrix phase if 16 w >= np_pad(B)).  W^R(tau)[A, B] streams
@@ -768,15 +1019,6 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // C~_A is stored in LDS in that slot order.  Shapes: 9-orbital species with
 // 49..64 product functions on both atoms.
 // ---------------------------------------------------------------------------
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-constexpr int kWBS = 72;                    // bf16 row stride of a W plane
-constexpr int kWBP = kMP * kWBS;            // bf16 elements per W plane
-constexpr int kCBS = 40;                    // bf16 per (plane, step, p) row of C~_A: 4 groups of 8 + pad
-
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
 
 __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3(
     const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
@@ -1059,7 +1301,9 @@ void launch_p_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
   const dim3 grid(grid_for(q.nblocks)), block(256);
 #define GWR_P(RT, CT, SHV, CA, CB)                                                                  \
   hipLaunchKernelGGL((p_mfma<RT, CT, SHV>), grid, block, 0, s, (const CT*)GR, (CT*)P, CA, CB, q, g)
-  if (p == GW_FP64) {
+  if (p == GW_BF16X3 && sh == 1) {
+    hipLaunchKernelGGL(p_bf16x3, grid, block, 0, s, (const float2*)GR, (float2*)P, A.Cpair32, B.Cpair32, q, g);
+  } else if (p == GW_FP64) {
     if (sh == 1)
       GWR_P(double, double2, 1, A.Cpair, B.Cpair);
     else if (sh == 2)

@@ -25,7 +25,8 @@ static bool force_generic() {
 
 gw_status launch_polarizability(const gw_cell* c, const void* GR, void* P, double g, gw_precision p,
                                 hipStream_t s) {
-  // GW_BF16X3 has no BF16 polarizability kernel yet: it runs the FP32 kernels (same storage types)
+  // GW_BF16X3: split-precision BF16 kernel for the 9-orbital / 49..64-function species
+  // pairs, the FP32 kernels for every other shape
   const bool gen = force_generic();
   for (int sa = 0; sa < c->n_species; ++sa)
     for (int sb = 0; sb < c->n_species; ++sb) {

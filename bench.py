@@ -33,14 +33,16 @@ HBM_PEAK = 8.0e12
 # the summaries are in profiles/).  Keyed by (kernel, precision); valid only while the
 # source file that defines the kernel has the recorded SHA-256 prefix, else reported null.
 TRAFFIC = {
-    ("Sigma", "fp32"): {"bytes": 62.62e9 + 3.35e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
-                        "sha256": "f4c650e2038e2010"},
-    ("P", "fp32"): {"bytes": 3.31e9 + 57.53e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
-                    "sha256": "f4c650e2038e2010"},
+    ("Sigma", "bf16x3"): {"bytes": 76.49e9 + 8.99e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
+                          "sha256": "50146b417ee12c4e"},
+    ("P", "bf16x3"): {"bytes": 3.04e9 + 59.76e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
+                      "sha256": "50146b417ee12c4e"},
+    ("drain_P", "bf16x3"): {"bytes": 64.54e9 + 78.52e9, "source": "paper_1911_05633_amd/csrc/omega_kernels.h",
+                            "sha256": "c18cd167d389bbc1"},
     ("drain_P", "fp32"): {"bytes": 64.73e9 + 78.24e9, "source": "paper_1911_05633_amd/csrc/omega_kernels.h",
                           "sha256": "c18cd167d389bbc1"},
-    ("k2r", "fp32"): {"bytes": 2.58e9 + 1.29e9, "source": "paper_1911_05633_amd/csrc/fourier.hip",
-                      "sha256": "a5af6e76c96c7ef9"},
+    ("k2r", "bf16x3"): {"bytes": 2.58e9 + 1.29e9, "source": "paper_1911_05633_amd/csrc/fourier.hip",
+                        "sha256": "a5af6e76c96c7ef9"},
 }
 
 

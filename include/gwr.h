@@ -144,6 +144,44 @@ gw_status gw_drain(const gw_cell* cell, const void* T, int n_omega, int parity, 
 gw_status gw_density(const gw_cell* cell, const void* G, gw_dtype g_type, int space, double spin_factor,
                      double* n_dev, void* stream);
 
+/* Real-space cutoff and distance tiers of the product basis (Sec. 2, Figs. 1 and 2).
+ * Plans the blocks (R, A, B) -- atom A in cell R, atom B in cell 0 -- that are kept:
+ * those whose centre distance d = |R' . a + r_A - r_B|, minimised over the lattice vectors
+ * R' equal to R modulo the mesh, is at most r_c (blocks farther apart are zero).  A kept
+ * block's product basis depends on d: all functions of both atoms when A = B in the same
+ * cell (R = 0); the first m_tier[2 s] functions of an atom of species s when 0 < d <= r_b;
+ * the first m_tier[2 s + 1] when r_b < d <= r_c.
+ *   lattice:   host [3][3], rows are the lattice vectors;
+ *   positions: host [n_atoms][3], Cartesian, same length unit;
+ *   m_tier:    host [n_species][2], each in [1, n_pb of the species].
+ * GW_ERR_ARG for r_b < 0, r_c < r_b, non-finite input, a bad tier size, or a mesh so coarse
+ * that some pair has two periodic images inside the sphere (the paper's k-mesh condition).
+ * Set-up call: it allocates device memory for the list (held until gw_cell_destroy) and
+ * replaces any earlier list of the cell; call it while no pair contraction of the cell is
+ * in flight. */
+gw_status gw_cell_set_pairs(gw_cell* cell, const double* lattice, const double* positions, double r_b,
+                            double r_c, const int* m_tier);
+
+/* The planned list: *n_pairs kept blocks and, when pairs != NULL, the first
+ * min(n_pairs, capacity) of them as host int [.][5] = (R, A, B, mA, mB), with mA, mB the
+ * product functions kept on atoms A and B.  GW_ERR_ARG without a list. */
+gw_status gw_cell_pairs(const gw_cell* cell, long long* n_pairs, int* pairs, long long capacity);
+
+/* Eq. (5) over the kept blocks only, every tau: P^R_IJ(tau) for I < mA, J < mB of each
+ * listed (R, A, B), zero for the other (I, J) of that block.  Blocks outside the list are
+ * not written: the caller zero-fills P once if it needs them.  Tensors, spin factor and
+ * storage types as gw_polarizability; FP64 arithmetic for GW_FP64, FP32 operands with FP64
+ * sums otherwise (GW_BF16X3 runs as GW_FP32).  Plain vector-ALU kernels, one workgroup per
+ * block.  GW_ERR_ARG without a list. */
+gw_status gw_polarizability_pairs(const gw_cell* cell, const void* GR, void* P, double spin_factor,
+                                  gw_precision prec, void* stream);
+
+/* Eq. (8) over the kept blocks only, every tau, with W^R_IJ taken as zero for I >= mA or
+ * J >= mB of the block.  Sigma blocks outside the list are not written.  Tensors and storage
+ * types as gw_self_energy; arithmetic as gw_polarizability_pairs. */
+gw_status gw_self_energy_pairs(const gw_cell* cell, const void* GR, const void* WR, void* Sigma,
+                               gw_precision prec, void* stream);
+
 /* Host helper: the FP64 matrix T[n_omega][n_tau] (complex, interleaved) that integrates
  * the piecewise-linear interpolant of F(tau) against exp(i omega_m tau) over [0, beta]
  * exactly (trapezoid rule at omega = 0).  tau: host, increasing; omega: host.

@@ -39,6 +39,10 @@ SIGNATURES = {
     "gw_drain": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _c_int, _vp]),
     "gw_density": (_c_int, [_vp, _vp, _c_int, _c_int, _c_double, _vp, _vp]),
     "gw_tau2omega_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
+    "gw_cell_set_pairs": (_c_int, [_vp, _dp, _dp, _c_double, _c_double, _ip]),
+    "gw_cell_pairs": (_c_int, [_vp, ctypes.POINTER(ctypes.c_longlong), _ip, ctypes.c_longlong]),
+    "gw_polarizability_pairs": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
+    "gw_self_energy_pairs": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_status_string": (ctypes.c_char_p, [_c_int]),
     "gw_last_error": (ctypes.c_char_p, []),
 }
@@ -141,6 +145,24 @@ class Cell:
         n = self.n_basis(basis)
         return (self.n_tau if lead is None else lead) * self.N_R * n * n
 
+    def set_pairs(self, lattice, positions, r_b, r_c, m_tier):
+        """Real-space cutoff and distance tiers (gw_cell_set_pairs); returns the number of
+        kept (R, A, B) blocks."""
+        lat = np.ascontiguousarray(lattice, dtype=np.float64).reshape(3, 3)
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        mt = np.ascontiguousarray(m_tier, dtype=np.int32).reshape(-1, 2)
+        _check(lib.gw_cell_set_pairs(self.handle, lat.ctypes.data_as(_dp), pos.ctypes.data_as(_dp), float(r_b),
+                                     float(r_c), mt.ctypes.data_as(_ip)), "gw_cell_set_pairs")
+        return len(self.pairs())
+
+    def pairs(self):
+        """The planned blocks as an int array [n][5] = (R, A, B, mA, mB)."""
+        n = ctypes.c_longlong()
+        _check(lib.gw_cell_pairs(self.handle, ctypes.byref(n), None, 0), "gw_cell_pairs")
+        out = np.zeros((n.value, 5), dtype=np.int32)
+        _check(lib.gw_cell_pairs(self.handle, ctypes.byref(n), out.ctypes.data_as(_ip), n.value), "gw_cell_pairs")
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             lib.gw_cell_destroy(self.handle)
@@ -189,6 +211,26 @@ def gw_self_energy(cell, GR, WR, Sigma, prec=None):
         raise TypeError("Sigma is always complex128")
     _check(lib.gw_self_energy(cell.handle, _ptr(GR, cell.elems(0), "GR"), _ptr(WR, cell.elems(1), "WR"),
                               _ptr(Sigma, cell.elems(0), "Sigma"), p, _stream()), "gw_self_energy")
+
+
+def gw_polarizability_pairs(cell, GR, P, spin_factor=2.0, prec=None):
+    p = _prec(prec, GR)
+    want = GW_C128 if p == GW_FP64 else GW_C64
+    if _dtype_code(GR) != want or _dtype_code(P) != want:
+        raise TypeError("GR and P must be complex128 for fp64 and complex64 otherwise")
+    _check(lib.gw_polarizability_pairs(cell.handle, _ptr(GR, cell.elems(0), "GR"), _ptr(P, cell.elems(1), "P"),
+                                       float(spin_factor), p, _stream()), "gw_polarizability_pairs")
+
+
+def gw_self_energy_pairs(cell, GR, WR, Sigma, prec=None):
+    p = _prec(prec, GR)
+    want = GW_C128 if p == GW_FP64 else GW_C64
+    if _dtype_code(GR) != want or _dtype_code(WR) != want:
+        raise TypeError("GR and WR must be complex128 for fp64 and complex64 otherwise")
+    if _dtype_code(Sigma) != GW_C128:
+        raise TypeError("Sigma is always complex128")
+    _check(lib.gw_self_energy_pairs(cell.handle, _ptr(GR, cell.elems(0), "GR"), _ptr(WR, cell.elems(1), "WR"),
+                                    _ptr(Sigma, cell.elems(0), "Sigma"), p, _stream()), "gw_self_energy_pairs")
 
 
 def _T_ptr(cell, T):

@@ -19,11 +19,24 @@ constexpr int kIch = 4;  // product functions per LDS chunk
 
 struct BlockIdx {
   int t, R, A, B;
+  int mA, mB;  // product functions kept on each side (all of them without a block list)
 };
 
+// Block b of the launch: every (t, R, iA, iB) in order, or, with a block list, (t, list
+// entry) with the entry (R, iA, iB, mA | mB << 16) of the real-space cutoff.
 __device__ __forceinline__ BlockIdx decode(long long b, int NR, int nA, int nB, const int* atomsA,
-                                           const int* atomsB) {
+                                           const int* atomsB, const int4* list, int nlist, int mA, int mB) {
   BlockIdx o;
+  if (list) {
+    const int4 e = list[b % nlist];
+    o.t = (int)(b / nlist);
+    o.R = e.x;
+    o.A = atomsA[e.y];
+    o.B = atomsB[e.z];
+    o.mA = e.w & 0xffff;
+    o.mB = e.w >> 16;
+    return o;
+  }
   const int iB = (int)(b % nB);
   b /= nB;
   const int iA = (int)(b % nA);
@@ -32,6 +45,8 @@ __device__ __forceinline__ BlockIdx decode(long long b, int NR, int nA, int nB, 
   o.t = (int)(b / NR);
   o.A = atomsA[iA];
   o.B = atomsB[iB];
+  o.mA = mA;
+  o.mB = mB;
   return o;
 }
 
@@ -41,10 +56,10 @@ __global__ __launch_bounds__(256) void p_generic(const CT* __restrict__ GR, CT* 
                                                  int mA, int nB, int mB, const int* atomsA, int cntA,
                                                  const int* atomsB, int cntB, const int* orb_off,
                                                  const int* pb_off, const int* minusR, int NR, int n_tau, int No,
-                                                 int Np, double g) {
+                                                 int Np, double g, const int4* list, int nlist) {
   __shared__ double2 X[kMaxOrb * kMaxOrb], Y[kMaxOrb * kMaxOrb];
   __shared__ double2 V[kIch * kMaxOrb * kMaxOrb], U[kIch * kMaxOrb * kMaxOrb];
-  const BlockIdx bi = decode(blockIdx.x, NR, cntA, cntB, atomsA, atomsB);
+  const BlockIdx bi = decode(blockIdx.x, NR, cntA, cntB, atomsA, atomsB, list, nlist, mA, mB);
   const int tm = n_tau - 1 - bi.t, mR = minusR[bi.R];
   const int oA = orb_off[bi.A], oB = orb_off[bi.B], pA = pb_off[bi.A], pB = pb_off[bi.B];
   const long long sl = (long long)No * No;
@@ -66,8 +81,9 @@ __global__ __launch_bounds__(256) void p_generic(const CT* __restrict__ GR, CT* 
   CT* Pblk = P + ((long long)bi.t * NR + bi.R) * Np * Np;
   for (int I0 = 0; I0 < mA; I0 += kIch) {
     const int ni = min(kIch, mA - I0);
+    const int nc = max(0, min(ni, bi.mA - I0));  // rows of this chunk inside the block's basis
     // V^I_ad
-    for (int i = threadIdx.x; i < ni * nA * nB; i += 256) {
+    for (int i = threadIdx.x; i < nc * nA * nB; i += 256) {
       const int il = i / (nA * nB), r = i % (nA * nB), a = r / nB, d = r % nB;
       const RT* Ci = CA + (long long)(I0 + il) * nA * nA + a * nA;
       double sr = 0, si = 0;
@@ -80,7 +96,7 @@ __global__ __launch_bounds__(256) void p_generic(const CT* __restrict__ GR, CT* 
     }
     __syncthreads();
     // U^I_cd
-    for (int i = threadIdx.x; i < ni * nB * nB; i += 256) {
+    for (int i = threadIdx.x; i < nc * nB * nB; i += 256) {
       const int il = i / (nB * nB), r = i % (nB * nB), c = r / nB, d = r % nB;
       double sr = 0, si = 0;
       for (int a = 0; a < nA; ++a) {
@@ -91,15 +107,17 @@ __global__ __launch_bounds__(256) void p_generic(const CT* __restrict__ GR, CT* 
       U[il * nB * nB + c * nB + d] = make_double2(sr, si);
     }
     __syncthreads();
-    // P_IJ
+    // P_IJ; zero outside the block's basis
     for (int i = threadIdx.x; i < ni * mB; i += 256) {
       const int il = i / mB, J = i % mB;
-      const RT* Cj = CB + (long long)J * nB * nB;
       double sr = 0, si = 0;
-      for (int cd = 0; cd < nB * nB; ++cd) {
-        const double2 u = U[il * nB * nB + cd];
-        sr += u.x * (double)Cj[cd];
-        si += u.y * (double)Cj[cd];
+      if (il < nc && J < bi.mB) {
+        const RT* Cj = CB + (long long)J * nB * nB;
+        for (int cd = 0; cd < nB * nB; ++cd) {
+          const double2 u = U[il * nB * nB + cd];
+          sr += u.x * (double)Cj[cd];
+          si += u.y * (double)Cj[cd];
+        }
       }
       stc(Pblk + (long long)(pA + I0 + il) * Np + pB + J, -g * sr, -g * si);
     }
@@ -112,10 +130,11 @@ __global__ __launch_bounds__(256) void s_generic(const CT* __restrict__ GR, cons
                                                  double2* __restrict__ S, const RT* __restrict__ CA,
                                                  const RT* __restrict__ CB, int nA, int mA, int nB, int mB,
                                                  const int* atomsA, int cntA, const int* atomsB, int cntB,
-                                                 const int* orb_off, const int* pb_off, int NR, int No, int Np) {
+                                                 const int* orb_off, const int* pb_off, int NR, int No, int Np,
+                                                 const int4* list, int nlist) {
   __shared__ double2 X[kMaxOrb * kMaxOrb];
   __shared__ double2 Z[kIch * kMaxOrb * kMaxOrb], Tt[kIch * kMaxOrb * kMaxOrb];
-  const BlockIdx bi = decode(blockIdx.x, NR, cntA, cntB, atomsA, atomsB);
+  const BlockIdx bi = decode(blockIdx.x, NR, cntA, cntB, atomsA, atomsB, list, nlist, mA, mB);
   const int oA = orb_off[bi.A], oB = orb_off[bi.B], pA = pb_off[bi.A], pB = pb_off[bi.B];
   const long long slG = (long long)No * No, slW = (long long)Np * Np;
   const CT* Gt = GR + ((long long)bi.t * NR + bi.R) * slG;
@@ -130,13 +149,14 @@ __global__ __launch_bounds__(256) void s_generic(const CT* __restrict__ GR, cons
   const int my_a = threadIdx.x / nB, my_b = threadIdx.x % nB;
   const bool owner = (int)threadIdx.x < nA * nB;
   __syncthreads();
-  for (int I0 = 0; I0 < mA; I0 += kIch) {
-    const int ni = min(kIch, mA - I0);
+  // W entries outside the block's basis (I >= mA, J >= mB of the cutoff tier) do not enter
+  for (int I0 = 0; I0 < bi.mA; I0 += kIch) {
+    const int ni = min(kIch, bi.mA - I0);
     for (int i = threadIdx.x; i < ni * nB * nB; i += 256) {
       const int il = i / (nB * nB), r = i % (nB * nB);
       const CT* Wrow = Wt + (long long)(pA + I0 + il) * Np + pB;
       double sr = 0, si = 0;
-      for (int J = 0; J < mB; ++J) {
+      for (int J = 0; J < bi.mB; ++J) {
         double wr, wi;
         ldc(Wrow + J, wr, wi);
         const double cj = (double)CB[(long long)J * nB * nB + r];
@@ -177,37 +197,60 @@ __global__ __launch_bounds__(256) void s_generic(const CT* __restrict__ GR, cons
 
 }  // namespace
 
-// Launch the generic kernels for one species pair.
-void launch_p_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
-                           double g, gw_precision p, hipStream_t s) {
-  const long long blocks = (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
+// Launch the generic kernels for one species pair, over every block or over a block list
+// (list != nullptr: n entries, n_tau blocks each).
+static void p_generic_launch(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                             const void* GR, void* P, double g, gw_precision p, hipStream_t s) {
+  const long long blocks = list ? (long long)c->n_tau * n
+                                : (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
   if (blocks == 0) return;
   if (p == GW_FP64)
     hipLaunchKernelGGL((p_generic<double2, double>), dim3((unsigned)blocks), dim3(256), 0, s, (const double2*)GR,
                        (double2*)P, A.C, B.C, A.n, A.m, B.n, B.m, A.atoms_dev, (int)A.atoms.size(), B.atoms_dev,
                        (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev, c->minusR_dev, c->N_R, c->n_tau,
-                       c->N_orb, c->N_pb, g);
+                       c->N_orb, c->N_pb, g, list, n);
   else
     hipLaunchKernelGGL((p_generic<float2, float>), dim3((unsigned)blocks), dim3(256), 0, s, (const float2*)GR,
                        (float2*)P, A.C32, B.C32, A.n, A.m, B.n, B.m, A.atoms_dev, (int)A.atoms.size(), B.atoms_dev,
                        (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev, c->minusR_dev, c->N_R, c->n_tau,
-                       c->N_orb, c->N_pb, g);
+                       c->N_orb, c->N_pb, g, list, n);
 }
 
-void launch_s_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
-                           const void* WR, void* S, gw_precision p, hipStream_t s) {
-  const long long blocks = (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
+static void s_generic_launch(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                             const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s) {
+  const long long blocks = list ? (long long)c->n_tau * n
+                                : (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
   if (blocks == 0) return;
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_generic<double2, double>), dim3((unsigned)blocks), dim3(256), 0, s, (const double2*)GR,
                        (const double2*)WR, (double2*)S, A.C, B.C, A.n, A.m, B.n, B.m, A.atoms_dev,
                        (int)A.atoms.size(), B.atoms_dev, (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev,
-                       c->N_R, c->N_orb, c->N_pb);
+                       c->N_R, c->N_orb, c->N_pb, list, n);
   else
     hipLaunchKernelGGL((s_generic<float2, float>), dim3((unsigned)blocks), dim3(256), 0, s, (const float2*)GR,
                        (const float2*)WR, (double2*)S, A.C32, B.C32, A.n, A.m, B.n, B.m, A.atoms_dev,
                        (int)A.atoms.size(), B.atoms_dev, (int)B.atoms.size(), c->orb_off_dev, c->pb_off_dev,
-                       c->N_R, c->N_orb, c->N_pb);
+                       c->N_R, c->N_orb, c->N_pb, list, n);
+}
+
+void launch_p_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
+                           double g, gw_precision p, hipStream_t s) {
+  p_generic_launch(c, A, B, nullptr, 0, GR, P, g, p, s);
+}
+
+void launch_s_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
+                           const void* WR, void* S, gw_precision p, hipStream_t s) {
+  s_generic_launch(c, A, B, nullptr, 0, GR, WR, S, p, s);
+}
+
+void launch_p_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                           const void* GR, void* P, double g, gw_precision p, hipStream_t s) {
+  if (n > 0) p_generic_launch(c, A, B, list, n, GR, P, g, p, s);
+}
+
+void launch_s_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                           const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s) {
+  if (n > 0) s_generic_launch(c, A, B, list, n, GR, WR, S, p, s);
 }
 
 }  // namespace gwr

@@ -58,6 +58,13 @@ struct gw_cell {
   int* species_dev = nullptr;
   std::vector<gwr::SpeciesDev> sp;
   std::vector<void*> owned;            // every device allocation, freed at destroy
+  // real-space cutoff (gw_cell_set_pairs): kept blocks (R, A, B, mA, mB) on the host, and per
+  // species pair (sa * n_species + sb) on the device as (R, index of A in its species, index
+  // of B in its species, mA | mB << 16)
+  bool pairs_set = false;
+  std::vector<int> pair_list;
+  std::vector<int4*> pair_dev;
+  std::vector<int> pair_cnt;
 };
 
 namespace gwr {
@@ -78,6 +85,11 @@ gw_status launch_drain(const gw_cell* c, const void* T, int n_omega, int parity,
                        void* out, gw_dtype ot, int n, hipStream_t s);
 gw_status launch_polarizability(const gw_cell* c, const void* GR, void* P, double g, gw_precision p,
                                 hipStream_t s);
+// plain kernels over a list of (R, iA, iB, mA | mB << 16) blocks of one species pair
+void launch_p_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                           const void* GR, void* P, double g, gw_precision p, hipStream_t s);
+void launch_s_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                           const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s);
 gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, void* S,
                              gw_precision p, hipStream_t s);
 gw_status launch_density(const gw_cell* c, const void* G, gw_dtype t, int space, double g, double* n_dev,

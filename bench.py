@@ -297,6 +297,61 @@ def serve_bench(args, torch, log):
     print(json.dumps(out), flush=True)
 
 
+def pairs_bench(args, torch, log):
+    """Real-space cutoff path (Sec. 2, Figs. 1 and 2): P + Sigma over the kept blocks of Si cells
+    of 8 to 72 atoms at one cutoff (r_b = 2.5 A, r_c = 4.6 A: each atom with itself, its 4
+    neighbours in the B tier with all 60 product functions and the 24 next ones in the C tier
+    with 16), beside the dense contraction of every (R, A, B) block of the same cell."""
+    import synthcell as sc
+    import paper_1911_05633_amd as g
+
+    prec = args.prec
+    rows = []
+    for kind in ("si8", "si24", "si40", "si72"):
+        spec = sc.serving_cell(kind, 48, 0)
+        d = build_inputs(spec, prec, torch, log)
+        cell = g.Cell.from_spec(spec, d["C"])
+        nk = cell.set_pairs(spec.lattice, spec.positions, 2.5, 4.6, [[60, 16]])
+        g.gw_fourier_k2r(cell, d["Gk"], d["GR"], basis=0)
+
+        def cut():
+            g.gw_polarizability_pairs(cell, d["GR"], d["P"], spec.spin, prec=prec)
+            g.gw_self_energy_pairs(cell, d["GR"], d["W"], d["S"], prec=prec)
+
+        def dense():
+            g.gw_polarizability(cell, d["GR"], d["P"], spec.spin, prec=prec)
+            g.gw_self_energy(cell, d["GR"], d["W"], d["S"], prec=prec)
+
+        def timed(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_cut, ms_dense = timed(cut), timed(dense)
+        row = {"cell": kind, "atoms": spec.n_atoms, "N_R": spec.N_R, "n_tau": spec.n_tau, "kept_blocks": nk,
+               "dense_blocks": spec.N_R * spec.n_atoms ** 2, "ms_cutoff": ms_cut, "ms_dense": ms_dense,
+               "us_per_kept_block_and_tau": ms_cut * 1e3 / (nk * spec.n_tau)}
+        log(f"cutoff {kind}: {row}")
+        rows.append(row)
+        del d, cell
+        torch.cuda.empty_cache()
+    a = np.array([r["atoms"] for r in rows], dtype=float)
+    t = np.array([r["ms_cutoff"] for r in rows])
+    slope = float(np.polyfit(np.log(a), np.log(t), 1)[0])
+    out = {"metric": "cutoff path: P+Sigma ms vs cell size at fixed r_c (plain kernels over the kept blocks)",
+           "unit": "ms", "n_gpus": 1, "dtype": prec, "data": "synthetic",
+           "config": {"workload": "Si cells of 8, 24, 40, 72 atoms, n_tau 48, r_b 2.5 A, r_c 4.6 A, "
+                                  "m_B 60, m_C 16", "prec": prec},
+           "rows": rows, "loglog_slope_time_vs_atoms": slope}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +367,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead of the step benchmark")
     ap.add_argument("--copy-ref", type=float, default=0.0, metavar="GIB",
                     help="only run one plain device copy of GIB GiB (counter reference) and exit")
+    ap.add_argument("--pairs", action="store_true",
+                    help="time the real-space cutoff path against the dense one on 8- to 72-atom cells and exit")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -332,6 +389,9 @@ def main():
         return
     if args.serve:
         serve_bench(args, torch, log)
+        return
+    if args.pairs:
+        pairs_bench(args, torch, log)
         return
     spec = sc.config(args.config)
     log(f"config {args.config}: {spec.name}, {spec.n_atoms} atoms, N_orb {spec.N_orb}, N_pb {spec.N_pb}, "

@@ -109,7 +109,74 @@ struct PairArgs {
   const int* minusR;
   int NR, n_tau, n_half, No, Np;
   long long nblocks;
+  // block list of the real-space cutoff (nullptr: every block): entry i is
+  // list[2 i] = (R, mA | mB << 16, first product function of A, first orbital of A),
+  // list[2 i + 1] = (first product function of B, first orbital of B, 0, 0)
+  const int4* list;
+  int nlist;
 };
+
+// Block walk shared by the kernels below.  Dense: every (tau, R, iA, iB) in counting order
+// (iB fastest), atom offsets from the per-species tables.  LIST: every (tau, list entry),
+// the entry index held in iA; R, the offsets and the kept product functions come from it.
+struct Blk {
+  int t, R, iA, iB;
+  int2 oa, ob;  // (first product function, first orbital) of atoms A and B
+  int mt;       // product functions kept on A and B, mA | mB << 16 (all of them when dense)
+};
+
+template <bool LIST>
+__device__ __forceinline__ void blk_start(Blk& k, long long b, const PairArgs& q) {
+  if constexpr (LIST) {
+    k.t = (int)(b / q.nlist);
+    k.iA = (int)(b - (long long)k.t * q.nlist);
+    k.iB = 0;
+    k.R = 0;
+  } else {
+    k.iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    k.iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    k.R = (int)(b % q.NR);
+    k.t = (int)(b / q.NR);
+  }
+}
+
+template <bool LIST>
+__device__ __forceinline__ void blk_step(Blk& k, const PairArgs& q) {
+  if constexpr (LIST) {
+    if (++k.iA == q.nlist) {
+      k.iA = 0;
+      ++k.t;
+    }
+  } else {
+    if (++k.iB == q.cntB) {
+      k.iB = 0;
+      if (++k.iA == q.cntA) {
+        k.iA = 0;
+        if (++k.R == q.NR) {
+          k.R = 0;
+          ++k.t;
+        }
+      }
+    }
+  }
+}
+
+template <bool LIST>
+__device__ __forceinline__ void blk_fill(Blk& k, const PairArgs& q) {
+  if constexpr (LIST) {
+    const int4 e0 = q.list[2 * k.iA], e1 = q.list[2 * k.iA + 1];
+    k.R = e0.x;
+    k.mt = e0.y;
+    k.oa = make_int2(e0.z, e0.w);
+    k.ob = make_int2(e1.x, e1.y);
+  } else {
+    k.oa = q.offsA[k.iA < q.cntA ? k.iA : 0];
+    k.ob = q.offsB[k.iB < q.cntB ? k.iB : 0];
+    k.mt = q.mA | (q.mB << 16);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // polarizability
@@ -120,7 +187,7 @@ constexpr int kCS = kPL + 1; // LDS row stride of C~_B (real): 16 consecutive ro
 
 // SH selects compile-time tile counts (no per-MFMA guards): 1 = np_pad 48 / m_pad 64 on both
 // atoms (9 orbitals, 49..64 product functions), 2 = np_pad 16 / m_pad 16; 0 = read from q.
-template <class RT, class CT, int SH>
+template <class RT, class CT, int SH, bool LIST = false>
 __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* __restrict__ P,
                                                  const RT* __restrict__ CpA, const RT* __restrict__ CpB,
                                                  const PairArgs q, double g) {
@@ -169,22 +236,6 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   // the entries of block b + 2 being loaded while block b is multiplied.
   __shared__ int mRs[kMaxR];
   for (int i = tid; i < q.NR; i += 256) mRs[i] = q.minusR[i];
-  struct Blk {
-    int t, R, iA, iB;
-    int2 oa, ob;  // (first product function, first orbital) of atoms A and B
-  };
-  auto advance = [&](Blk& k) {
-    if (++k.iB == q.cntB) {
-      k.iB = 0;
-      if (++k.iA == q.cntA) {
-        k.iA = 0;
-        if (++k.R == q.NR) {
-          k.R = 0;
-          ++k.t;
-        }
-      }
-    }
-  };
   // the X and Y tiles of the next block are loaded into registers (one element per thread,
   // n_A n_B <= 81 < 256) while the current block is on the matrix cores
   CT xr, yr;  // kept in the storage type until stored to LDS (no wait at the load)
@@ -210,23 +261,13 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
   Blk cur;
-  {
-    long long b = bbeg < q.nblocks ? bbeg : 0;
-    cur.iB = (int)(b % q.cntB);
-    b /= q.cntB;
-    cur.iA = (int)(b % q.cntA);
-    b /= q.cntA;
-    cur.R = (int)(b % q.NR);
-    cur.t = (int)(b / q.NR);
-  }
-  cur.oa = q.offsA[cur.iA];
-  cur.ob = q.offsB[cur.iB];
+  blk_start<LIST>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  blk_fill<LIST>(cur, q);
   Blk nxt = cur, nn = cur;
-  advance(nxt);
-  nxt.oa = q.offsA[nxt.iA < q.cntA ? nxt.iA : 0];
-  nxt.ob = q.offsB[nxt.iB < q.cntB ? nxt.iB : 0];
-  advance(nn);
-  advance(nn);
+  blk_step<LIST>(nxt, q);
+  blk_fill<LIST>(nxt, q);
+  blk_step<LIST>(nn, q);
+  blk_step<LIST>(nn, q);
   __syncthreads();  // minus-R table staged
   if (bbeg < bend) {
     fetch(cur);
@@ -241,8 +282,8 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
     const int pA = k.oa.x, pB = k.ob.x;
     const bool more = blk + 1 < bend;
     if (more) fetch(nxt);
-    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
-    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
+    Blk nf = nn;
+    blk_fill<LIST>(nf, q);
     // Q over unordered pairs (zero outside the live pairs); the pair tables of this
     // thread's entries are held in registers
 #pragma unroll
@@ -330,7 +371,9 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
           for (int j = 0; j < 4; ++j) {
             const int J = 16 * Jt + M::drow(lk, j);
             if (Jt < nJT && J < q.mB) {
-              const double re = -g * (double)acc2[Jt][0][j], im = -g * (double)acc2[Jt][1][j];
+              // a listed block keeps I < mA, J < mB of its tier and is zero elsewhere
+              const bool kp = !LIST || (I < (k.mt & 0xffff) && J < (k.mt >> 16));
+              const double re = kp ? -g * (double)acc2[Jt][0][j] : 0.0, im = kp ? -g * (double)acc2[Jt][1][j] : 0.0;
               stc(Pd + (long long)(pA + I) * q.Np + pB + J, re, im);
               if (t != tm) stc(Pm + (long long)(pB + J) * q.Np + pA + I, re, im);
             }
@@ -339,10 +382,8 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
     }
     if (more) stage();  // Xs, Ys were last read before the barrier above
     cur = nxt;
-    nxt = nn;
-    nxt.oa = noa;
-    nxt.ob = nob;
-    advance(nn);
+    nxt = nf;
+    blk_step<LIST>(nn, q);
     __syncthreads();
   }
 }
@@ -372,6 +413,7 @@ constexpr int kQBS = 72;              // bf16 row stride of a Q^T plane
 constexpr int kQBP = kPL * kQBS;      // bf16 elements per plane
 constexpr int kCBB = 40;              // bf16 per (plane, step, J) row of C~_B
 
+template <bool LIST = false>
 __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR, float2* __restrict__ P,
                                                    const float* __restrict__ CpA, const float* __restrict__ CpB,
                                                    const PairArgs q, double g) {
@@ -423,22 +465,6 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
   }
   __builtin_amdgcn_s_waitcnt(0);
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
-  struct Blk {
-    int t, R, iA, iB;
-    int2 oa, ob;
-  };
-  auto advance = [&](Blk& k) {
-    if (++k.iB == q.cntB) {
-      k.iB = 0;
-      if (++k.iA == q.cntA) {
-        k.iA = 0;
-        if (++k.R == q.NR) {
-          k.R = 0;
-          ++k.t;
-        }
-      }
-    }
-  };
   float2 xr, yr;
   const bool xok = tid < q.nA * q.nB;
   auto fetch = [&](const Blk& k) {
@@ -459,23 +485,13 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
   Blk cur;
-  {
-    long long b = bbeg < q.nblocks ? bbeg : 0;
-    cur.iB = (int)(b % q.cntB);
-    b /= q.cntB;
-    cur.iA = (int)(b % q.cntA);
-    b /= q.cntA;
-    cur.R = (int)(b % q.NR);
-    cur.t = (int)(b / q.NR);
-  }
-  cur.oa = q.offsA[cur.iA];
-  cur.ob = q.offsB[cur.iB];
+  blk_start<LIST>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  blk_fill<LIST>(cur, q);
   Blk nxt = cur, nn = cur;
-  advance(nxt);
-  nxt.oa = q.offsA[nxt.iA < q.cntA ? nxt.iA : 0];
-  nxt.ob = q.offsB[nxt.iB < q.cntB ? nxt.iB : 0];
-  advance(nn);
-  advance(nn);
+  blk_step<LIST>(nxt, q);
+  blk_fill<LIST>(nxt, q);
+  blk_step<LIST>(nn, q);
+  blk_step<LIST>(nn, q);
   if (bbeg < bend) {
     fetch(cur);
     stage();
@@ -502,8 +518,8 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
     const int pA = k.oa.x, pB = k.ob.x;
     const bool more = blk + 1 < bend;
     if (more) fetch(nxt);
-    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
-    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
+    Blk nf = nn;
+    blk_fill<LIST>(nf, q);
     // Q over unordered pairs, written split and transposed
 #pragma unroll
     for (int e = 0; e < kQE; ++e) {
@@ -581,7 +597,8 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
           for (int j = 0; j < 4; ++j) {
             const int J = 16 * Jt + 4 * lk + j;
             if (J < q.mB) {
-              const double re = -g * (double)acc2[Jt][0][j], im = -g * (double)acc2[Jt][1][j];
+              const bool kp = !LIST || (I < (k.mt & 0xffff) && J < (k.mt >> 16));
+              const double re = kp ? -g * (double)acc2[Jt][0][j] : 0.0, im = kp ? -g * (double)acc2[Jt][1][j] : 0.0;
               stc(Pd + (long long)(pA + I) * q.Np + pB + J, re, im);
               if (t != tm) stc(Pm + (long long)(pB + J) * q.Np + pA + I, re, im);
             }
@@ -590,10 +607,8 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
     }
     if (more) stage();
     cur = nxt;
-    nxt = nn;
-    nxt.oa = noa;
-    nxt.ob = nob;
-    advance(nn);
+    nxt = nf;
+    blk_step<LIST>(nn, q);
     __syncthreads();
   }
 }
@@ -795,7 +810,7 @@ constexpr int kIT32 = kMP / 16;
 
 // NIT = m_pad(A) / 16, NKJ = m_pad(B) / 4, NMT = np_pad(A) / 16 are compile-time so that
 // every operand array stays in registers.
-template <int NIT, int NKJ, int NMT>
+template <int NIT, int NKJ, int NMT, bool LIST = false>
 __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_mfma32(
     const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
     const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
@@ -824,22 +839,6 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   // Blocks are walked in a contiguous range, so their (tau, R, iA, iB) indices advance by
   // counting (B fastest) and the atom offsets come from the per-species (pb, orb) tables;
   // the table entries of block b + 2 are loaded while block b is multiplied.
-  struct Blk {
-    int t, R, iA, iB;
-    int2 oa, ob;  // (first product function, first orbital) of atoms A and B
-  };
-  auto advance = [&](Blk& k) {
-    if (++k.iB == q.cntB) {
-      k.iB = 0;
-      if (++k.iA == q.cntA) {
-        k.iA = 0;
-        if (++k.R == q.NR) {
-          k.R = 0;
-          ++k.t;
-        }
-      }
-    }
-  };
   // W rows r = w + 3 u (64 consecutive elements of a row per wavefront), column = lane
   float2 wreg[kW32PF];
   float2 xr;
@@ -858,11 +857,13 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int a = tid / q.nB, c = tid - a * q.nB;
     xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
   };
-  auto stash = [&]() {
+  // mt: product functions kept by the block whose W is staged (W outside them is zero)
+  auto stash = [&](int mt) {
 #pragma unroll
     for (int u = 0; u < kW32PF; ++u) {
       const int r = w + 3 * u;
-      if (r < kMP) Wb[r * kW32S + lane] = keep(wreg[u], r < q.mA && lane_ok);
+      const bool tier = !LIST || (r < (mt & 0xffff) && lane < (mt >> 16));
+      if (r < kMP) Wb[r * kW32S + lane] = keep(wreg[u], r < q.mA && lane_ok && tier);
     }
     if (xok) Xs[tid] = xr;
   };
@@ -891,29 +892,17 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
   Blk cur;
-  {
-    long long b = bbeg < q.nblocks ? bbeg : 0;
-    cur.iB = (int)(b % q.cntB);
-    b /= q.cntB;
-    cur.iA = (int)(b % q.cntA);
-    b /= q.cntA;
-    cur.R = (int)(b % q.NR);
-    cur.t = (int)(b / q.NR);
-  }
-  auto offsets = [&](Blk& k) {
-    k.oa = q.offsA[k.iA];
-    k.ob = q.offsB[k.iB];
-  };
-  offsets(cur);
+  blk_start<LIST>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  blk_fill<LIST>(cur, q);
   Blk nxt = cur, nn = cur;
-  advance(nxt);
-  if (bbeg + 1 < bend) offsets(nxt);
-  advance(nn);
-  advance(nn);
+  blk_step<LIST>(nxt, q);
+  blk_fill<LIST>(nxt, q);
+  blk_step<LIST>(nn, q);
+  blk_step<LIST>(nn, q);
   if (bbeg < bend) {
     fetch(cur);
     fetch_x(cur);
-    stash();
+    stash(cur.mt);
   }
   __syncthreads();
   for (long long blk = bbeg; blk < bend; ++blk) {
@@ -926,8 +915,8 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     }
     // offsets of block blk + 2 (always loaded, from in-range indices, so that nothing
     // copies the registers before the end of this block), consumed by the next fetch
-    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
-    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
+    Blk nf = nn;
+    blk_fill<LIST>(nf, q);
     f4 acc2[3][2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = f4{0, 0, 0, 0};
@@ -990,16 +979,14 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     sr += __shfl_xor(sr, 1);
     si += __shfl_xor(si, 1);
     __syncthreads();  // K and X no longer read
-    if (more) stash();
+    if (more) stash(nxt.mt);
     if (live && uh == 0) {
       const int a = uo / q.nB, bb = uo - a * q.nB;
       S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
     }
     cur = nxt;
-    nxt = nn;
-    nxt.oa = noa;
-    nxt.ob = nob;
-    advance(nn);
+    nxt = nf;
+    blk_step<LIST>(nn, q);
     __syncthreads();
   }
 }
@@ -1020,6 +1007,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // 49..64 product functions on both atoms.
 // ---------------------------------------------------------------------------
 
+template <bool LIST = false>
 __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3(
     const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
     const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
@@ -1057,22 +1045,6 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
   const int half_a = (q.nA + 1) / 2;
   const int uo = tid >> 1, uh = tid & 1;
-  struct Blk {
-    int t, R, iA, iB;
-    int2 oa, ob;
-  };
-  auto advance = [&](Blk& k) {
-    if (++k.iB == q.cntB) {
-      k.iB = 0;
-      if (++k.iA == q.cntA) {
-        k.iA = 0;
-        if (++k.R == q.NR) {
-          k.R = 0;
-          ++k.t;
-        }
-      }
-    }
-  };
   float2 wreg[kW32PF];
   float2 xr;
   const bool lane_ok = lane < q.mB;
@@ -1090,12 +1062,14 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     const int a = tid / q.nB, c = tid - a * q.nB;
     xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
   };
-  auto stash = [&]() {
+  // mt: product functions kept by the block whose W is staged (W outside them is zero)
+  auto stash = [&](int mt) {
 #pragma unroll
     for (int u = 0; u < kW32PF; ++u) {
       const int r = w + 3 * u;
       if (r < kMP) {
-        const float2 v = keep(wreg[u], r < q.mA && lane_ok);
+        const bool tier = !LIST || (r < (mt & 0xffff) && lane < (mt >> 16));
+        const float2 v = keep(wreg[u], r < q.mA && lane_ok && tier);
         __bf16 h, l;
         split_bf16(v.x, h, l);
         Wp[0 * kWBP + r * kWBS + lane] = h;
@@ -1161,27 +1135,17 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
   Blk cur;
-  {
-    long long b = bbeg < q.nblocks ? bbeg : 0;
-    cur.iB = (int)(b % q.cntB);
-    b /= q.cntB;
-    cur.iA = (int)(b % q.cntA);
-    b /= q.cntA;
-    cur.R = (int)(b % q.NR);
-    cur.t = (int)(b / q.NR);
-  }
-  cur.oa = q.offsA[cur.iA];
-  cur.ob = q.offsB[cur.iB];
+  blk_start<LIST>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  blk_fill<LIST>(cur, q);
   Blk nxt = cur, nn = cur;
-  advance(nxt);
-  nxt.oa = q.offsA[nxt.iA < q.cntA ? nxt.iA : 0];
-  nxt.ob = q.offsB[nxt.iB < q.cntB ? nxt.iB : 0];
-  advance(nn);
-  advance(nn);
+  blk_step<LIST>(nxt, q);
+  blk_fill<LIST>(nxt, q);
+  blk_step<LIST>(nn, q);
+  blk_step<LIST>(nn, q);
   if (bbeg < bend) {
     fetch(cur);
     fetch_x(cur);
-    stash();
+    stash(cur.mt);
   }
   __syncthreads();
   for (long long blk = bbeg; blk < bend; ++blk) {
@@ -1192,8 +1156,8 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       fetch(nxt);
       fetch_x(nxt);
     }
-    const int2 noa = q.offsA[nn.iA < q.cntA ? nn.iA : 0];
-    const int2 nob = q.offsB[nn.iB < q.cntB ? nn.iB : 0];
+    Blk nf = nn;
+    blk_fill<LIST>(nf, q);
     f4 acc2[3][2];
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = f4{0, 0, 0, 0};
@@ -1239,16 +1203,14 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     sr += __shfl_xor(sr, 1);
     si += __shfl_xor(si, 1);
     __syncthreads();  // K and X no longer read
-    if (more) stash();
+    if (more) stash(nxt.mt);
     if (live && uh == 0) {
       const int a = uo / q.nB, bb = uo - a * q.nB;
       S[((long long)k.t * q.NR + k.R) * sl + (long long)(oA + a) * q.No + oB + bb] = make_double2(-sr, -si);
     }
     cur = nxt;
-    nxt = nn;
-    nxt.oa = noa;
-    nxt.ob = nob;
-    advance(nn);
+    nxt = nf;
+    blk_step<LIST>(nn, q);
     __syncthreads();
   }
 }
@@ -1280,6 +1242,8 @@ PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, i
   q.No = c->N_orb;
   q.Np = c->N_pb;
   q.nblocks = (long long)n_half * c->N_R * q.cntA * q.cntB;
+  q.list = nullptr;
+  q.nlist = 0;
   return q;
 }
 
@@ -1344,6 +1308,70 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
   else
     hipLaunchKernelGGL((s_mfma<float, float2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+}
+
+// The same kernels over a block list of the real-space cutoff (entries as in PairArgs::list).
+// Every P shape the dense launcher handles is covered; Sigma is covered for the FP32 and
+// BF16 kernels of the 9-orbital and small shapes, and the caller uses the plain kernels
+// when this returns false.
+bool launch_p_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                        const void* GR, void* P, double g, gw_precision p, hipStream_t s) {
+  PairArgs q = make_args(c, A, B, (c->n_tau + 1) / 2);
+  q.list = list;
+  q.nlist = n;
+  q.nblocks = (long long)q.n_half * n;
+  if (q.nblocks == 0) return true;
+  const int sh = (A.np_pad == 48 && B.np_pad == 48 && A.m_pad == 64 && (B.m + 15) / 16 == 4)   ? 1
+                 : (A.np_pad == 16 && B.np_pad == 16 && A.m_pad == 16 && (B.m + 15) / 16 == 1) ? 2
+                                                                                              : 0;
+  const dim3 grid(grid_for(q.nblocks)), block(256);
+#define GWR_P(RT, CT, SHV, CA, CB)                                                                  \
+  hipLaunchKernelGGL((p_mfma<RT, CT, SHV, true>), grid, block, 0, s, (const CT*)GR, (CT*)P, CA, CB, q, g)
+  if (p == GW_BF16X3 && sh == 1) {
+    hipLaunchKernelGGL(p_bf16x3<true>, grid, block, 0, s, (const float2*)GR, (float2*)P, A.Cpair32, B.Cpair32, q,
+                       g);
+  } else if (p == GW_FP64) {
+    if (sh == 1)
+      GWR_P(double, double2, 1, A.Cpair, B.Cpair);
+    else if (sh == 2)
+      GWR_P(double, double2, 2, A.Cpair, B.Cpair);
+    else
+      GWR_P(double, double2, 0, A.Cpair, B.Cpair);
+  } else {
+    if (sh == 1)
+      GWR_P(float, float2, 1, A.Cpair32, B.Cpair32);
+    else if (sh == 2)
+      GWR_P(float, float2, 2, A.Cpair32, B.Cpair32);
+    else
+      GWR_P(float, float2, 0, A.Cpair32, B.Cpair32);
+  }
+#undef GWR_P
+  return true;
+}
+
+bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                        const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s) {
+  if (p == GW_FP64) return false;
+  const bool si = A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48;
+  const bool small = A.m_pad == 16 && B.m_pad == 16 && A.np_pad == 16;
+  if (!si && !small) return false;
+  PairArgs q = make_args(c, A, B, c->n_tau);
+  q.list = list;
+  q.nlist = n;
+  q.nblocks = (long long)c->n_tau * n;
+  if (q.nblocks == 0) return true;
+  const long long g32 = 6LL * c->n_cu;
+  const unsigned grid32 = (unsigned)(q.nblocks < g32 ? q.nblocks : g32);
+  if (p == GW_BF16X3 && si)
+    hipLaunchKernelGGL(s_bf16x3<true>, dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR, (const float2*)WR,
+                       (double2*)S, A.Cpair32, B.Cpair32, q);
+  else if (si)
+    hipLaunchKernelGGL((s_mfma32<4, 16, 3, true>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
+                       (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+  else
+    hipLaunchKernelGGL((s_mfma32<1, 4, 1, true>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
+                       (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+  return true;
 }
 
 }  // namespace gwr

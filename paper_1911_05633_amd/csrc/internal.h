@@ -64,6 +64,7 @@ struct gw_cell {
   bool pairs_set = false;
   std::vector<int> pair_list;
   std::vector<int4*> pair_dev;
+  std::vector<int4*> pair_dev_mfma;    // same blocks as two int4 each (see launch_p_mfma_list)
   std::vector<int> pair_cnt;
 };
 
@@ -90,6 +91,13 @@ void launch_p_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesD
                            const void* GR, void* P, double g, gw_precision p, hipStream_t s);
 void launch_s_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
                            const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s);
+// matrix-core kernels over a list of (R, mA | mB << 16, pb A, orb A), (pb B, orb B, 0, 0)
+// entries; false when the shape / precision has no list kernel
+bool mfma_pair_ok(const SpeciesDev& A, const SpeciesDev& B);
+bool launch_p_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                        const void* GR, void* P, double g, gw_precision p, hipStream_t s);
+bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                        const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s);
 gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, void* S,
                              gw_precision p, hipStream_t s);
 gw_status launch_density(const gw_cell* c, const void* G, gw_dtype t, int space, double g, double* n_dev,

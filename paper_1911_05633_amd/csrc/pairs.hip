@@ -8,6 +8,8 @@
 // sphere.  A kept block uses all product functions of both atoms when A = B in the same
 // cell, the first m_B of each atom when 0 < d <= r_b and the first m_C when r_b < d <= r_c.
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "internal.h"
@@ -35,6 +37,12 @@ gw_status cell_on_device(const gw_cell* c) {
   if (hipGetDevice(&cur) != hipSuccess) return fail(GW_ERR_HIP, "hipGetDevice failed");
   if (cur != c->device) return fail(GW_ERR_ARG, "current device differs from the cell's device");
   return GW_OK;
+}
+
+// GWR_KERNELS=generic selects the plain kernels, as for the dense entry points
+bool force_generic() {
+  const char* v = std::getenv("GWR_KERNELS");
+  return v && std::strcmp(v, "generic") == 0;
 }
 
 double norm3(const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
@@ -91,6 +99,7 @@ gw_status gw_cell_set_pairs(gw_cell* c, const double* lattice, const double* pos
   }
   std::vector<int> host;
   std::vector<std::vector<int4>> groups((size_t)c->n_species * c->n_species);
+  std::vector<std::vector<int4>> groups2((size_t)c->n_species * c->n_species);
   std::vector<int> index_in_species(c->n_atoms, 0);
   for (int s = 0; s < c->n_species; ++s)
     for (size_t i = 0; i < c->sp[s].atoms.size(); ++i) index_in_species[c->sp[s].atoms[i]] = (int)i;
@@ -133,17 +142,23 @@ gw_status gw_cell_set_pairs(gw_cell* c, const double* lattice, const double* pos
             host.insert(host.end(), {R, A, B, mA, mB});
             groups[(size_t)sA * c->n_species + sB].push_back(
                 make_int4(R, index_in_species[A], index_in_species[B], mA | (mB << 16)));
+            auto& g2 = groups2[(size_t)sA * c->n_species + sB];
+            g2.push_back(make_int4(R, mA | (mB << 16), c->pb_off[A], c->orb_off[A]));
+            g2.push_back(make_int4(c->pb_off[B], c->orb_off[B], 0, 0));
           }
       }
-  std::vector<int4*> dev(groups.size(), nullptr);
+  std::vector<int4*> dev(groups.size(), nullptr), dev2(groups.size(), nullptr);
   std::vector<int> cnt(groups.size(), 0);
   for (size_t g = 0; g < groups.size(); ++g) {
     cnt[g] = (int)groups[g].size();
     st = upload_owned(c, &dev[g], groups[g].data(), groups[g].size());
     if (st != GW_OK) return st;
+    st = upload_owned(c, &dev2[g], groups2[g].data(), groups2[g].size());
+    if (st != GW_OK) return st;
   }
   c->pair_list.swap(host);
   c->pair_dev.swap(dev);
+  c->pair_dev_mfma.swap(dev2);
   c->pair_cnt.swap(cnt);
   c->pairs_set = true;
   return GW_OK;
@@ -183,8 +198,12 @@ gw_status gw_polarizability_pairs(const gw_cell* c, const void* GR, void* P, dou
   for (int sa = 0; sa < c->n_species; ++sa)
     for (int sb = 0; sb < c->n_species; ++sb) {
       const size_t gi = (size_t)sa * c->n_species + sb;
-      launch_p_generic_list(c, c->sp[sa], c->sp[sb], c->pair_dev[gi], c->pair_cnt[gi], GR, P, g, prec,
-                            (hipStream_t)stream);
+      const SpeciesDev &A = c->sp[sa], &B = c->sp[sb];
+      if (c->pair_cnt[gi] == 0) continue;
+      if (!force_generic() && mfma_pair_ok(A, B) && mfma_pair_ok(B, A))
+        launch_p_mfma_list(c, A, B, c->pair_dev_mfma[gi], c->pair_cnt[gi], GR, P, g, prec, (hipStream_t)stream);
+      else
+        launch_p_generic_list(c, A, B, c->pair_dev[gi], c->pair_cnt[gi], GR, P, g, prec, (hipStream_t)stream);
     }
   return check_launch("polarizability over the pair list");
 }
@@ -203,8 +222,11 @@ gw_status gw_self_energy_pairs(const gw_cell* c, const void* GR, const void* WR,
   for (int sa = 0; sa < c->n_species; ++sa)
     for (int sb = 0; sb < c->n_species; ++sb) {
       const size_t gi = (size_t)sa * c->n_species + sb;
-      launch_s_generic_list(c, c->sp[sa], c->sp[sb], c->pair_dev[gi], c->pair_cnt[gi], GR, WR, S, prec,
-                            (hipStream_t)stream);
+      const SpeciesDev &A = c->sp[sa], &B = c->sp[sb];
+      if (c->pair_cnt[gi] == 0) continue;
+      if (force_generic() || !mfma_pair_ok(A, B) ||
+          !launch_s_mfma_list(c, A, B, c->pair_dev_mfma[gi], c->pair_cnt[gi], GR, WR, S, prec, (hipStream_t)stream))
+        launch_s_generic_list(c, A, B, c->pair_dev[gi], c->pair_cnt[gi], GR, WR, S, prec, (hipStream_t)stream);
     }
   return check_launch("self-energy over the pair list");
 }

@@ -298,8 +298,8 @@ def serve_bench(args, torch, log):
 
 
 def pairs_bench(args, torch, log):
-    """Real-space cutoff path (Sec. 2, Figs. 1 and 2): P + Sigma over the kept blocks of Si cells
-    of 8 to 72 atoms at one cutoff (r_b = 2.5 A, r_c = 4.6 A: each atom with itself, its 4
+    """Real-space cutoff path (Sec. 2, Figs. 1 and 2): P + Sigma over the kept blocks (the
+    matrix-core kernels walking the block list) of Si cells of 8 to 72 atoms at one cutoff (r_b = 2.5 A, r_c = 4.6 A: each atom with itself, its 4
     neighbours in the B tier with all 60 product functions and the 24 next ones in the C tier
     with 16), beside the dense contraction of every (R, A, B) block of the same cell."""
     import synthcell as sc
@@ -344,7 +344,7 @@ def pairs_bench(args, torch, log):
     a = np.array([r["atoms"] for r in rows], dtype=float)
     t = np.array([r["ms_cutoff"] for r in rows])
     slope = float(np.polyfit(np.log(a), np.log(t), 1)[0])
-    out = {"metric": "cutoff path: P+Sigma ms vs cell size at fixed r_c (plain kernels over the kept blocks)",
+    out = {"metric": "cutoff path: P+Sigma ms vs cell size at fixed r_c (kernels walking the kept-block list)",
            "unit": "ms", "n_gpus": 1, "dtype": prec, "data": "synthetic",
            "config": {"workload": "Si cells of 8, 24, 40, 72 atoms, n_tau 48, r_b 2.5 A, r_c 4.6 A, "
                                   "m_B 60, m_C 16", "prec": prec},

@@ -628,7 +628,7 @@ constexpr int kKS = kPL + 1;                     // K row stride (complex)
 constexpr int kSThreads = 192;
 constexpr int kWPT = (16 * kMP + kSThreads - 1) / kSThreads;
 
-template <class RT, class CT>
+template <class RT, class CT, bool LIST = false>
 __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_mfma(const CT* __restrict__ GR, const CT* __restrict__ WR,
                                                  double2* __restrict__ S, const RT* __restrict__ CpA,
                                                  const RT* __restrict__ CpB, const PairArgs q) {
@@ -654,26 +654,44 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   const int half_a = (q.nA + 1) / 2;
   const int uo = tid >> 1, uh = tid & 1;
 
-  struct Blk {
-    int t, R, A, B;
+  // block b: (tau, R, atoms) in counting order, or (tau, list entry) with LIST.  Dense: pA, pB
+  // hold the atoms (offsets looked up at use, as few live registers as possible); LIST: the
+  // offsets themselves and the kept product functions mt = mA | mB << 16.
+  struct SBlk {
+    int t, R, pA, oA, pB, oB, mt;
   };
   auto decode = [&](long long b) {
-    Blk o;
-    const int iB = (int)(b % q.cntB);
-    b /= q.cntB;
-    const int iA = (int)(b % q.cntA);
-    b /= q.cntA;
-    o.R = (int)(b % q.NR);
-    o.t = (int)(b / q.NR);
-    o.A = q.atomsA[iA];
-    o.B = q.atomsB[iB];
+    SBlk o;
+    if constexpr (LIST) {
+      o.t = (int)(b / q.nlist);
+      const int i = (int)(b - (long long)o.t * q.nlist);
+      const int4 e0 = q.list[2 * i], e1 = q.list[2 * i + 1];
+      o.R = e0.x;
+      o.mt = e0.y;
+      o.pA = e0.z;
+      o.oA = e0.w;
+      o.pB = e1.x;
+      o.oB = e1.y;
+    } else {
+      const int iB = (int)(b % q.cntB);
+      b /= q.cntB;
+      const int iA = (int)(b % q.cntA);
+      b /= q.cntA;
+      o.R = (int)(b % q.NR);
+      o.t = (int)(b / q.NR);
+      o.pA = q.atomsA[iA];
+      o.pB = q.atomsB[iB];
+      o.oA = o.oB = o.mt = 0;
+    }
     return o;
   };
   CT wreg[kWPT];  // prefetched W tile and X element, in the storage type
   CT xr;
   int wtile = 0;  // I tile of the W values in wreg (their validity is applied at stash())
-  auto fetch = [&](const Blk& k, int it) {
-    const CT* Wt = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)q.pb_off[k.A] * q.Np + q.pb_off[k.B];
+  int wmt = 0;    // product functions kept by the block of those W values
+  auto fetch = [&](const SBlk& k, int it) {
+    const int pa = LIST ? k.pA : q.pb_off[k.pA], pb = LIST ? k.pB : q.pb_off[k.pB];
+    const CT* Wt = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)pa * q.Np + pb;
 #pragma unroll
     for (int u = 0; u < kWPT; ++u) {
       const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP, I = 16 * it + r;
@@ -681,19 +699,21 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       wreg[u] = ldraw(Wt + (long long)I * q.Np + c, WR, ok);
     }
     wtile = it;
+    if constexpr (LIST) wmt = k.mt;
   };
   const bool xok = tid < q.nA * q.nB;
-  auto fetch_x = [&](const Blk& k) {
+  auto fetch_x = [&](const SBlk& k) {
     const int a = tid / q.nB, c = tid - a * q.nB;
-    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(q.orb_off[k.A] + a) * q.No + q.orb_off[k.B] + c,
-               GR, xok);
+    const int oa = LIST ? k.oA : q.orb_off[k.pA], ob = LIST ? k.oB : q.orb_off[k.pB];
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(oa + a) * q.No + ob + c, GR, xok);
   };
   auto stash = [&]() {
 #pragma unroll
     for (int u = 0; u < kWPT; ++u) {
       const int i = tid + kSThreads * u, r = i / kMP, c = i - r * kMP, I = 16 * wtile + r;
       if (r < 16) {
-        const CT v = keep(wreg[u], I < q.mA && c < q.mB);
+        const bool tier = !LIST || (I < (wmt & 0xffff) && c < (wmt >> 16));
+        const CT v = keep(wreg[u], I < q.mA && c < q.mB && tier);
         Wb[r * kWS + c] = mk<RT>((double)v.x, (double)v.y);
       }
     }
@@ -710,8 +730,8 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   }
   __syncthreads();
   for (long long blk = blockIdx.x; blk < q.nblocks; blk += gridDim.x) {
-    const Blk k = decode(blk);
-    const int oA = q.orb_off[k.A], oB = q.orb_off[k.B];
+    const SBlk k = decode(blk);
+    const int oA = LIST ? k.oA : q.orb_off[k.pA], oB = LIST ? k.oB : q.orb_off[k.pB];
     const bool more = blk + gridDim.x < q.nblocks;
     typename M::acc acc2[3][2];
 #pragma unroll
@@ -747,7 +767,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       }
     }
     if (more) {
-      const Blk kn = decode(blk + gridDim.x);
+      const SBlk kn = decode(blk + gridDim.x);
       fetch(kn, 0);
       fetch_x(kn);
     }
@@ -1310,10 +1330,9 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
                        (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
 }
 
-// The same kernels over a block list of the real-space cutoff (entries as in PairArgs::list).
-// Every P shape the dense launcher handles is covered; Sigma is covered for the FP32 and
-// BF16 kernels of the 9-orbital and small shapes, and the caller uses the plain kernels
-// when this returns false.
+// The same kernels over a block list of the real-space cutoff (entries as in PairArgs::list),
+// for every shape and precision the dense launchers handle (the caller uses the plain
+// kernels for shapes outside mfma_pair_ok).
 bool launch_p_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
                         const void* GR, void* P, double g, gw_precision p, hipStream_t s) {
   PairArgs q = make_args(c, A, B, (c->n_tau + 1) / 2);
@@ -1351,10 +1370,8 @@ bool launch_p_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
 
 bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
                         const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s) {
-  if (p == GW_FP64) return false;
   const bool si = A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48;
   const bool small = A.m_pad == 16 && B.m_pad == 16 && A.np_pad == 16;
-  if (!si && !small) return false;
   PairArgs q = make_args(c, A, B, c->n_tau);
   q.list = list;
   q.nlist = n;
@@ -1362,7 +1379,13 @@ bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
   if (q.nblocks == 0) return true;
   const long long g32 = 6LL * c->n_cu;
   const unsigned grid32 = (unsigned)(q.nblocks < g32 ? q.nblocks : g32);
-  if (p == GW_BF16X3 && si)
+  if (p == GW_FP64)
+    hipLaunchKernelGGL((s_mfma<double, double2, true>), dim3(grid_for(q.nblocks)), dim3(kSThreads), 0, s,
+                       (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);
+  else if (!si && !small)
+    hipLaunchKernelGGL((s_mfma<float, float2, true>), dim3(grid_for(q.nblocks)), dim3(kSThreads), 0, s,
+                       (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
+  else if (p == GW_BF16X3 && si)
     hipLaunchKernelGGL(s_bf16x3<true>, dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR, (const float2*)WR,
                        (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (si)

@@ -412,6 +412,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 constexpr int kQBS = 72;              // bf16 row stride of a Q^T plane
 constexpr int kQBP = kPL * kQBS;      // bf16 elements per plane
 constexpr int kCBB = 40;              // bf16 per (plane, step, J) row of C~_B
+constexpr int kTS = 33;               // complex row stride of a wavefront's output staging tile
 
 template <bool LIST = false>
 __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR, float2* __restrict__ P,
@@ -420,6 +421,7 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
   __shared__ float2 Xs[kMaxOrb * kMaxOrb], Ys[kMaxOrb * kMaxOrb];
   __shared__ __align__(16) __bf16 Qb[4 * kQBP];                // [part][hi|lo][p'][p]
   __shared__ __align__(16) __bf16 Cbb[2 * 2 * kMP * kCBB];     // [hi|lo][step][J][slot]
+  __shared__ __align__(16) float2 Ts[4 * 16 * kTS];            // [wavefront][I][J half]
   __shared__ unsigned char ta[kPL], tb[kPL], tc[kPL], td[kPL];
   __shared__ int mRs[kMaxR];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -589,8 +591,46 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
           }
         }
       }
+      // Lane (li, lk) holds J = 16 Jt + 4 lk + j of row I.  The mirror block's rows (J) take
+      // these as 128-byte runs directly.  The direct block's rows (I) go through a per-wave LDS
+      // tile, one 32-column half at a time, and leave as 16-byte stores along J.
       const int I = 16 * w + li;
-      if (I < q.mA) {
+      const float gf = (float)(-g);
+      float2* Tw = Ts + w * 16 * kTS;
+      const bool ev = ((q.Np | pB) & 1) == 0;
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int Jl = 16 * jt + 4 * lk + j, J = 32 * hf + Jl;
+            const bool kp = !LIST || (I < (k.mt & 0xffff) && J < (k.mt >> 16));
+            const f4& ar = acc2[2 * hf + jt][0];
+            const f4& ai = acc2[2 * hf + jt][1];
+            Tw[li * kTS + Jl] = kp ? make_float2(gf * ar[j], gf * ai[j]) : make_float2(0.f, 0.f);
+          }
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int rr = (lane >> 4) + 4 * it, Jl = 2 * (lane & 15), J = 32 * hf + Jl, Ir = 16 * w + rr;
+          if (Ir < q.mA && J < q.mB) {
+            const float2 v0 = Tw[rr * kTS + Jl];
+            float2* dst = Pd + (long long)(pA + Ir) * q.Np + pB + J;
+            if (J + 1 < q.mB) {
+              const float2 v1 = Tw[rr * kTS + Jl + 1];
+              if (ev) {
+                *reinterpret_cast<float4*>(dst) = make_float4(v0.x, v0.y, v1.x, v1.y);
+              } else {
+                dst[0] = v0;
+                dst[1] = v1;
+              }
+            } else {
+              dst[0] = v0;
+            }
+          }
+        }
+      }
+      if (t != tm && I < q.mA) {
 #pragma unroll
         for (int Jt = 0; Jt < 4; ++Jt)
 #pragma unroll
@@ -598,9 +638,8 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
             const int J = 16 * Jt + 4 * lk + j;
             if (J < q.mB) {
               const bool kp = !LIST || (I < (k.mt & 0xffff) && J < (k.mt >> 16));
-              const double re = kp ? -g * (double)acc2[Jt][0][j] : 0.0, im = kp ? -g * (double)acc2[Jt][1][j] : 0.0;
-              stc(Pd + (long long)(pA + I) * q.Np + pB + J, re, im);
-              if (t != tm) stc(Pm + (long long)(pB + J) * q.Np + pA + I, re, im);
+              Pm[(long long)(pB + J) * q.Np + pA + I] =
+                  kp ? make_float2(gf * acc2[Jt][0][j], gf * acc2[Jt][1][j]) : make_float2(0.f, 0.f);
             }
           }
       }

@@ -15,7 +15,9 @@ It computes, slowly and by the plain definitions of Kutepov's paper:
 * the imaginary-time to Matsubara-frequency transform F(i w) = int_0^beta
   exp(i w tau) F(tau) dtau of the piecewise-linear interpolant of F;
 * the electron count from G(R = 0, beta^-);
-* the real-space cutoff and distance tiers of the product basis (Sec. 2, Figs. 1, 2).
+* the real-space cutoff and distance tiers of the product basis (Sec. 2, Figs. 1, 2);
+* the screened interaction W~ = W - V from Eq. (2), and the inverse of the tau -> Matsubara
+  matrix.
 
 Conventions (the paper leaves them open; the readings are the same as the
 product library's documented ones):
@@ -40,3 +42,4 @@ from .matsubara import (  # noqa: F401
 from .density import electron_count  # noqa: F401
 from . import bruteforce  # noqa: F401
 from .cutoff import plan_pairs, polarizability_r_block_cut, self_energy_r_block_cut  # noqa: F401
+from .dyson import screened_interaction, omega_to_tau_matrix  # noqa: F401

@@ -1,0 +1,88 @@
+"""Pins of the screened-interaction oracle (Eq. (2)) and of the inverse tau transform."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.dyson import screened_interaction, omega_to_tau_matrix
+
+
+def _hpd(rng, n, shift=0.5):
+    B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    return B @ B.conj().T / n + shift * np.eye(n)
+
+
+def test_scalar_closed_form():
+    v, p = 1.7, -0.35 + 0.1j
+    W = screened_interaction(np.array([[[v]]]), np.array([[[[p]]]]))
+    assert abs(W[0, 0, 0, 0] - v * v * p / (1 - v * p)) < 1e-15
+
+
+def test_zero_polarizability_gives_zero():
+    rng = np.random.default_rng(1)
+    V = np.stack([_hpd(rng, 6) for _ in range(2)])
+    W = screened_interaction(V, np.zeros((3, 2, 6, 6), dtype=complex))
+    assert np.max(np.abs(W)) == 0.0
+
+
+def test_rank_one_sherman_morrison():
+    rng = np.random.default_rng(2)
+    n = 7
+    V = _hpd(rng, n)
+    u = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    P = -np.outer(u, u.conj())
+    W = screened_interaction(V[None], P[None, None])[0, 0]
+    Vu = V @ u
+    ref = -np.outer(Vu, Vu.conj()) / (1.0 + (u.conj() @ Vu))
+    assert np.max(np.abs(W - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_diagonal_case():
+    rng = np.random.default_rng(3)
+    v = rng.uniform(0.5, 2.0, 5)
+    p = -rng.uniform(0.0, 1.0, 5) + 0.2j * rng.standard_normal(5)
+    W = screened_interaction(np.diag(v)[None], np.diag(p)[None, None])[0, 0]
+    assert np.max(np.abs(W - np.diag(v * v * p / (1 - v * p)))) < 1e-14
+
+
+def test_neumann_series_for_weak_screening():
+    rng = np.random.default_rng(4)
+    n = 8
+    V = _hpd(rng, n)
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    P = -X @ X.conj().T
+    P *= 1e-4 / np.linalg.norm(V @ P, 2)
+    W = screened_interaction(V[None], P[None, None])[0, 0]
+    VP = V @ P
+    ref = VP @ V + VP @ VP @ V + VP @ VP @ VP @ V
+    # the first dropped term is (V P)^4 V, about 1e-16 of V here
+    assert np.max(np.abs(W - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_hermitian_inputs_give_hermitian_result():
+    rng = np.random.default_rng(5)
+    n = 9
+    V = np.stack([_hpd(rng, n) for _ in range(2)])
+    X = rng.standard_normal((3, 2, n, n)) + 1j * rng.standard_normal((3, 2, n, n))
+    P = -np.einsum("mqij,mqkj->mqik", X, X.conj()) / n
+    W = screened_interaction(V, P)
+    assert np.max(np.abs(W - np.conj(np.swapaxes(W, -1, -2)))) < 1e-12 * np.max(np.abs(W))
+
+
+@pytest.mark.parametrize("kind", ["bosonic", "fermionic"])
+def test_inverse_tau_transform(kind):
+    beta, n = 40.0, 16
+    u = np.linspace(0.0, 1.0, n)
+    tau = beta * (0.5 - 0.5 * np.cos(np.pi * u))   # symmetric, denser at the ends
+    om = oracle.bosonic_frequencies(n, beta) if kind == "bosonic" else oracle.fermionic_frequencies(n, beta)
+    Ti = omega_to_tau_matrix(tau, om)
+    T = oracle.filon_matrix(tau, om)
+    assert np.max(np.abs(Ti @ T - np.eye(n))) < 1e-10
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    assert np.max(np.abs(Ti @ oracle.apply_tau_to_omega(T, f) - f)) < 1e-9 * np.max(np.abs(f))
+
+
+def test_inverse_needs_square():
+    tau = np.linspace(0.0, 10.0, 8)
+    with pytest.raises(ValueError):
+        omega_to_tau_matrix(tau, oracle.bosonic_frequencies(6, 10.0))

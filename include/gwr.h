@@ -170,9 +170,10 @@ gw_status gw_cell_pairs(const gw_cell* cell, long long* n_pairs, int* pairs, lon
 /* Eq. (5) over the kept blocks only, every tau: P^R_IJ(tau) for I < mA, J < mB of each
  * listed (R, A, B), zero for the other (I, J) of that block.  Blocks outside the list are
  * not written: the caller zero-fills P once if it needs them.  Tensors, spin factor and
- * storage types as gw_polarizability; FP64 arithmetic for GW_FP64, FP32 operands with FP64
- * sums otherwise (GW_BF16X3 runs as GW_FP32).  Plain vector-ALU kernels, one workgroup per
- * block.  GW_ERR_ARG without a list. */
+ * storage types as gw_polarizability.  The matrix-core kernels of gw_polarizability run over
+ * the list where the block shape has one (precision as there); other shapes run plain
+ * vector-ALU kernels (FP64 for GW_FP64, FP32 operands with FP64 sums otherwise).  GW_ERR_ARG
+ * without a list. */
 gw_status gw_polarizability_pairs(const gw_cell* cell, const void* GR, void* P, double spin_factor,
                                   gw_precision prec, void* stream);
 
@@ -188,6 +189,38 @@ gw_status gw_self_energy_pairs(const gw_cell* cell, const void* GR, const void* 
  * T_host: host buffer of 2*n_omega*n_tau doubles. */
 gw_status gw_tau2omega_matrix(int n_tau, const double* tau, int n_omega, const double* omega,
                               double* T_host);
+
+/* Screened interaction, Eq. (2): at every momentum q and bosonic frequency nu the solution of
+ * W = V + V P W, returned as its screening part W~ = W - V (Sec. 2 splits W = V + W~; W~ is
+ * what Eq. (8) takes):
+ *   W~(q, nu) = (I - V(q) P(q, nu))^-1 V(q) - V(q) = (V(q)^-1 - P(q, nu))^-1 - V(q).
+ *   V:  DEVICE complex128 [N_k][N_pb][N_pb], Hermitian positive definite (bare Coulomb);
+ *   P:  DEVICE [n_omega][N_k][N_pb][N_pb] in p_type storage (the layout gw_drain leaves with
+ *       basis 1); each P(q, nu) Hermitian negative semidefinite, as at bosonic Matsubara
+ *       frequencies, so that V^-1 - P is Hermitian positive definite;
+ *   W:  DEVICE, P's shape, w_type storage; may be P itself when p_type == w_type, else disjoint;
+ *   work, work_size: DEVICE scratch of at least gw_screened_interaction_workspace(cell, 1)
+ *       bytes, owned by the caller and not retained; more lets more (q, nu) matrices be
+ *       inverted per launch (up to the size for chunk = n_omega * N_k);
+ *   info: NULL, or a DEVICE int set to 0, then to -(q + 1) if V(q) or to 1 + nu * N_k + q if
+ *       V(q)^-1 - P(q, nu) met a pivot that is not a positive real (one such matrix is named;
+ *       its output is then meaningless).  Read it after the stream completes.
+ * Both inverses are blocked Gauss-Jordan eliminations without pivoting, in FP64, on the
+ * matrices padded to a multiple of 64 with the identity.  Enqueued on `stream`. */
+gw_status gw_screened_interaction(const gw_cell* cell, const void* V, const void* P, gw_dtype p_type, void* W,
+                                  gw_dtype w_type, int n_omega, void* work, size_t work_size, int* info,
+                                  void* stream);
+
+/* Workspace bytes gw_screened_interaction needs to invert `chunk` (q, nu) matrices per launch:
+ * 16 * (Np^2 * (N_k + chunk) + 4096 * max(N_k, chunk)), Np = N_pb rounded up to 64. */
+gw_status gw_screened_interaction_workspace(const gw_cell* cell, int chunk, size_t* bytes);
+
+/* Host helper: the inverse of gw_tau2omega_matrix(n_tau, tau, n_omega, omega) (needs
+ * n_omega == n_tau), FP64 Gauss-Jordan with partial pivoting.  With it, gw_tau2omega (parity
+ * 0, n_omega = n_tau) takes frequency samples back to the tau samples of the piecewise-linear
+ * function whose transform they are.  Ti_host: 2 * n_tau * n_tau doubles.  GW_ERR_SHAPE when
+ * n_omega != n_tau, GW_ERR_ARG for a singular matrix. */
+gw_status gw_omega2tau_matrix(int n_tau, const double* tau, int n_omega, const double* omega, double* Ti_host);
 
 const char* gw_status_string(gw_status s);
 const char* gw_last_error(void);

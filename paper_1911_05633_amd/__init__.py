@@ -43,6 +43,9 @@ SIGNATURES = {
     "gw_cell_pairs": (_c_int, [_vp, ctypes.POINTER(ctypes.c_longlong), _ip, ctypes.c_longlong]),
     "gw_polarizability_pairs": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
     "gw_self_energy_pairs": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
+    "gw_screened_interaction": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_int, _c_int, _vp, ctypes.c_size_t, _vp, _vp]),
+    "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "gw_omega2tau_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
     "gw_status_string": (ctypes.c_char_p, [_c_int]),
     "gw_last_error": (ctypes.c_char_p, []),
 }
@@ -50,7 +53,7 @@ SIGNATURES = {
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1911_05633_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_1911_05633_amd/build.py`")
     # Tensors handed to the library are device pointers of torch's HIP runtime, so the
     # library must bind to that same runtime: torch (which loads its own libamdhip64)
     # goes first, and libgwr's libamdhip64.so.7 dependency then resolves to it instead
@@ -276,6 +279,50 @@ def gw_tau2omega_matrix(tau, omega):
     out = np.zeros((len(omega), len(tau)), dtype=np.complex128)
     _check(lib.gw_tau2omega_matrix(len(tau), tau.ctypes.data_as(_dp), len(omega), omega.ctypes.data_as(_dp),
                                    out.ctypes.data_as(_dp)), "gw_tau2omega_matrix")
+    return out
+
+
+def gw_screened_interaction_workspace(cell, chunk=1):
+    """Workspace bytes for `chunk` (q, nu) matrices per launch."""
+    b = ctypes.c_size_t()
+    _check(lib.gw_screened_interaction_workspace(cell.handle, int(chunk), ctypes.byref(b)),
+           "gw_screened_interaction_workspace")
+    return b.value
+
+
+def gw_screened_interaction(cell, V, P, W, work, info=None):
+    """W~(q, nu) = (I - V(q) P(q, nu))^-1 V(q) - V(q) for P of shape [n_omega][N_k][N_pb][N_pb].
+
+    V: complex128 device [N_k][N_pb][N_pb]; work: a device tensor (any dtype) used as scratch;
+    info: optional int32 device tensor of one element (see the header)."""
+    torch = _torch()
+    n = cell.N_pb
+    per = cell.N_R * n * n
+    if P.numel() % per or P.numel() == 0:
+        raise ValueError("P must hold n_omega * N_k * N_pb^2 elements")
+    n_omega = P.numel() // per
+    if V.dtype != torch.complex128:
+        raise TypeError("V must be complex128")
+    if not work.is_cuda or not work.is_contiguous():
+        raise ValueError("work must be a contiguous device tensor")
+    ip = None
+    if info is not None:
+        if info.dtype != torch.int32 or info.numel() != 1:
+            raise ValueError("info must be a one-element int32 device tensor")
+        ip = _ptr(info, 1, "info")
+    _check(lib.gw_screened_interaction(cell.handle, _ptr(V, per, "V"), _ptr(P, P.numel(), "P"), _dtype_code(P),
+                                       _ptr(W, P.numel(), "W"), _dtype_code(W), n_omega,
+                                       ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size(), ip,
+                                       _stream()), "gw_screened_interaction")
+
+
+def gw_omega2tau_matrix(tau, omega):
+    """Host FP64 inverse of gw_tau2omega_matrix(tau, omega) (numpy complex128 [n_tau][n_tau])."""
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros((len(tau), len(tau)), dtype=np.complex128)
+    _check(lib.gw_omega2tau_matrix(len(tau), tau.ctypes.data_as(_dp), len(omega), omega.ctypes.data_as(_dp),
+                                   out.ctypes.data_as(_dp)), "gw_omega2tau_matrix")
     return out
 
 

@@ -1,6 +1,6 @@
 """Build libgwr.so (gfx950) in-tree with hipcc.
 
-    python -m paper_1911_05633_amd.build          # or build() from Python
+    python paper_1911_05633_amd/build.py          # or __graft_entry__.build()
 
 Every .hip source under csrc/ is compiled to an object in parallel, then linked
 into paper_1911_05633_amd/libgwr.so.  Packed-FP32 instructions are disabled for

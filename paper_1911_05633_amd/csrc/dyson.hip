@@ -1,0 +1,377 @@
+// Screened interaction, Eq. (2): W = V + V P W at every (q, nu), returned as its screening
+// part W~ = W - V (the part Eq. (8) consumes; Sec. 2 splits W = V + W~).
+//
+// With V Hermitian positive definite and P(q, nu) Hermitian negative semidefinite (bosonic
+// Matsubara frequencies), W = (I - V P)^-1 V = (V^-1 - P)^-1 and V^-1 - P is Hermitian
+// positive definite, so both inverses are taken by Gauss-Jordan elimination without
+// pivoting, in FP64, blocked by 64:
+//   per block step k (K = the 64 indices of block k), on M in place:
+//     D = M[K,K]^-1                     (one workgroup per matrix, LDS)
+//     M[K,J] = D M[K,J]          J != K (row panel)
+//     M[I,J] -= M[I,K] M[K,J]    I, J != K (rank-64 update, the bulk of the work)
+//     M[I,K] = -M[I,K] D         I != K (column panel);  M[K,K] = D
+// Matrices are padded to a multiple of 64 with the identity, whose inverse is itself.
+// Work: 8 n^3 real flops per inversion (n^3 complex multiply-adds).
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace gwr {
+namespace {
+
+constexpr int kDB = 64;   // block size of the elimination
+constexpr int kKC = 16;   // depth of one LDS stage of a 64 x 64 tile product
+constexpr int kDS = 65;   // complex row stride of the diagonal block in LDS
+
+__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
+__device__ __forceinline__ double2 ld2(const float2* p) {
+  const float2 v = *p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+__global__ void dy_zero_info(int* info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *info = 0;
+}
+
+// mode 0: M[c] = V[q0 + c];  mode 1: M[c] = Vinv[q] - P[g] with g = g0 + c, q = g mod N_k.
+// Indices beyond n hold the identity.
+template <class PT>
+__global__ __launch_bounds__(256) void dy_load(double2* __restrict__ M, long long per, int np, int n, int mode,
+                                               const double2* __restrict__ Vsrc, const PT* __restrict__ P,
+                                               long long g0, int n_k) {
+  const int c = blockIdx.y;
+  const long long g = g0 + c;
+  const int q = mode == 0 ? (int)g : (int)(g % n_k);
+  double2* Mc = M + (long long)c * per;
+  const long long nn = (long long)np * np;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / np), j = (int)(e - (long long)i * np);
+    double2 v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    if (i < n && j < n) {
+      if (mode == 0) {
+        v = Vsrc[((long long)q * n + i) * n + j];
+      } else {
+        const double2 a = Vsrc[(long long)q * per + e];
+        const double2 p = ld2(P + (g * n + i) * n + j);
+        v = make_double2(a.x - p.x, a.y - p.y);
+      }
+    }
+    Mc[e] = v;
+  }
+}
+
+// W[g] = M[c] - V[q] on the n x n corner
+template <class WT>
+__global__ __launch_bounds__(256) void dy_store(const double2* __restrict__ M, long long per, int np, int n,
+                                                const double2* __restrict__ V, WT* __restrict__ W, long long g0,
+                                                int n_k) {
+  const int c = blockIdx.y;
+  const long long g = g0 + c;
+  const int q = (int)(g % n_k);
+  const long long nn = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+    const double2 a = M[(long long)c * per + (long long)i * np + j];
+    const double2 v = V[(long long)q * nn + e];
+    st2(W + g * nn + e, make_double2(a.x - v.x, a.y - v.y));
+  }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Inverse of the diagonal block of step k by in-place Gauss-Jordan; written to Dinv[c] and to
+// M[c][K,K].  A pivot that is not a positive real number flags the matrix in *info.
+__global__ __launch_bounds__(256) void dy_diag(double2* __restrict__ M, double2* __restrict__ Dinv, long long per,
+                                               int np, int k, int* info, int code0, int sign) {
+  __shared__ double2 D[kDB * kDS];
+  __shared__ double2 Rw[kDB], Fc[kDB];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  double2* Mk = M + (long long)c * per + (long long)k * kDB * np + (long long)k * kDB;
+  for (int e = tid; e < kDB * kDB; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    D[i * kDS + j] = Mk[(long long)i * np + j];
+  }
+  __syncthreads();
+  const int i = tid >> 2, j0 = tid & 3;
+  for (int p = 0; p < kDB; ++p) {
+    const double2 piv = D[p * kDS + p];
+    const double den = piv.x * piv.x + piv.y * piv.y;
+    const double2 inv = make_double2(piv.x / den, -piv.y / den);
+    if (tid == 0 && info && !(piv.x > 0.0 && std::isfinite(piv.x) && std::isfinite(piv.y)))
+      atomicCAS(info, 0, sign * (code0 + c + 1));
+    if (tid < kDB) {
+      Rw[tid] = tid == p ? inv : cmul(D[p * kDS + tid], inv);
+    } else if (tid < 2 * kDB) {
+      const int r = tid - kDB;
+      Fc[r] = r == p ? make_double2(0.0, 0.0) : D[r * kDS + p];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int jj = 0; jj < kDB / 4; ++jj) {
+      const int j = j0 + 4 * jj;
+      if (i == p) {
+        D[p * kDS + j] = Rw[j];
+      } else {
+        const double2 b = j == p ? make_double2(0.0, 0.0) : D[i * kDS + j];
+        const double2 f = Fc[i], r = Rw[j];
+        D[i * kDS + j] = make_double2(b.x - (f.x * r.x - f.y * r.y), b.y - (f.x * r.y + f.y * r.x));
+      }
+    }
+    __syncthreads();
+  }
+  double2* Dc = Dinv + (long long)c * kDB * kDB;
+  for (int e = tid; e < kDB * kDB; e += 256) {
+    const int r = e >> 6, s = e & 63;
+    const double2 v = D[r * kDS + s];
+    Dc[e] = v;
+    Mk[(long long)r * np + s] = v;
+  }
+}
+
+// 64 x 64 tile products of one block step (grid.z = matrix):
+//   OP 0: M[K,J] = D M[K,J]        (grid.x = J tile)
+//   OP 1: M[I,J] -= M[I,K] M[K,J]  (grid.x = J tile, grid.y = I tile)
+//   OP 2: M[I,K] = -M[I,K] D       (grid.x = I tile)
+// Thread (ty, tx) = (tid / 16, tid % 16) owns rows ty + 16 a and columns tx + 16 b of the tile.
+// A tile that is both read and written belongs to one workgroup, which reads all of it before
+// the last barrier and writes after it.
+template <int OP>
+__global__ __launch_bounds__(256) void dy_tile(double2* __restrict__ M, const double2* __restrict__ Dinv,
+                                               long long per, int np, int k) {
+  __shared__ double2 As[kDB * (kKC + 1)];
+  __shared__ double2 Bs[kKC * kDB];
+  const int c = blockIdx.z, tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  double2* Mc = M + (long long)c * per;
+  const double2* Dc = Dinv + (long long)c * kDB * kDB;
+  const long long K0 = (long long)k * kDB;
+  const double2 *A, *B;
+  long long lda, ldb;
+  double2* C;
+  if (OP == 0) {
+    const int J = blockIdx.x;
+    if (J == k) return;
+    A = Dc;
+    lda = kDB;
+    B = Mc + K0 * np + (long long)J * kDB;
+    ldb = np;
+    C = Mc + K0 * np + (long long)J * kDB;
+  } else if (OP == 1) {
+    const int J = blockIdx.x, I = blockIdx.y;
+    if (I == k || J == k) return;
+    A = Mc + (long long)I * kDB * np + K0;
+    lda = np;
+    B = Mc + K0 * np + (long long)J * kDB;
+    ldb = np;
+    C = Mc + (long long)I * kDB * np + (long long)J * kDB;
+  } else {
+    const int I = blockIdx.x;
+    if (I == k) return;
+    A = Mc + (long long)I * kDB * np + K0;
+    lda = np;
+    B = Dc;
+    ldb = kDB;
+    C = Mc + (long long)I * kDB * np + K0;
+  }
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < kDB; k0 += kKC) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      const int ai = e >> 4, ak = e & 15;
+      As[ai * (kKC + 1) + ak] = A[(long long)ai * lda + k0 + ak];
+      const int bk = e >> 6, bj = e & 63;
+      Bs[bk * kDB + bj] = B[(long long)(k0 + bk) * ldb + bj];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kKC; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[(ty + 16 * a) * (kKC + 1) + kk];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk * kDB + tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b].x = fma(av[a].x, bv[b].x, fma(-av[a].y, bv[b].y, acc[a][b].x));
+          acc[a][b].y = fma(av[a].x, bv[b].y, fma(av[a].y, bv[b].x, acc[a][b].y));
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double2* d = C + (long long)(ty + 16 * a) * np + tx + 16 * b;
+      if (OP == 0) {
+        *d = acc[a][b];
+      } else if (OP == 1) {
+        const double2 v = *d;
+        *d = make_double2(v.x - acc[a][b].x, v.y - acc[a][b].y);
+      } else {
+        *d = make_double2(-acc[a][b].x, -acc[a][b].y);
+      }
+    }
+}
+
+unsigned grid_elems(long long n) {
+  const long long b = (n + 255) / 256;
+  return (unsigned)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+// in-place inverse of `count` padded matrices M[c] (stride per); info codes sign * (code0 + c + 1)
+gw_status gj_invert(double2* M, double2* Dinv, int count, int np, int* info, int code0, int sign, hipStream_t s) {
+  const long long per = (long long)np * np;
+  const int nt = np / kDB;
+  for (int k = 0; k < nt; ++k) {
+    hipLaunchKernelGGL(dy_diag, dim3(count), dim3(256), 0, s, M, Dinv, per, np, k, info, code0, sign);
+    if (nt > 1) {
+      hipLaunchKernelGGL(dy_tile<0>, dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL(dy_tile<1>, dim3(nt, nt, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL(dy_tile<2>, dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
+    }
+  }
+  return check_launch("screened interaction: elimination");
+}
+
+int padded(int n) { return (n + kDB - 1) / kDB * kDB; }
+
+size_t work_bytes(int n_k, int np, long long chunk) {
+  const long long nd = chunk > n_k ? chunk : n_k;
+  return 16 * ((size_t)np * np * (size_t)(n_k + chunk) + (size_t)kDB * kDB * (size_t)nd);
+}
+
+bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
+  auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return !(x < y + nb && y < x + na);
+}
+
+}  // namespace
+}  // namespace gwr
+
+using namespace gwr;
+
+extern "C" {
+
+gw_status gw_screened_interaction_workspace(const gw_cell* c, int chunk, size_t* bytes) {
+  if (!c || !bytes) return fail(GW_ERR_ARG, "NULL pointer");
+  if (chunk < 1) return fail(GW_ERR_ARG, "chunk must be >= 1");
+  *bytes = work_bytes(c->N_R, padded(c->N_pb), chunk);
+  return GW_OK;
+}
+
+gw_status gw_screened_interaction(const gw_cell* c, const void* V, const void* P, gw_dtype pt, void* W, gw_dtype wt,
+                                  int n_omega, void* work, size_t work_size, int* info, void* stream) {
+  if (!c) return fail(GW_ERR_ARG, "cell is NULL");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(GW_ERR_HIP, "hipGetDevice failed");
+  if (cur != c->device) return fail(GW_ERR_ARG, "current device differs from the cell's device");
+  if (!V || !P || !W || !work) return fail(GW_ERR_ARG, "NULL pointer");
+  if ((pt != GW_C128 && pt != GW_C64) || (wt != GW_C128 && wt != GW_C64)) return fail(GW_ERR_ARG, "bad dtype");
+  if (n_omega < 1) return fail(GW_ERR_SHAPE, "n_omega must be >= 1");
+  const int n_k = c->N_R, n = c->N_pb, np = padded(n);
+  const long long total = (long long)n_omega * n_k;
+  long long chunk = 0;
+  if (work_size >= work_bytes(n_k, np, 1)) {
+    long long lo = 1, hi = total;
+    while (lo < hi) {
+      const long long mid = (lo + hi + 1) / 2;
+      if (work_bytes(n_k, np, mid) <= work_size) lo = mid; else hi = mid - 1;
+    }
+    chunk = lo;
+  }
+  if (chunk < 1) return fail(GW_ERR_SHAPE, "workspace smaller than gw_screened_interaction_workspace(cell, 1)");
+  if (chunk > 65535) chunk = 65535;
+  const size_t nv = (size_t)n_k * n * n * 16, npw = (size_t)total * n * n;
+  const size_t bp = npw * csize(pt), bw = npw * csize(wt), bwork = work_bytes(n_k, np, chunk);
+  if (!disjoint(V, nv, W, bw) || !disjoint(work, bwork, V, nv) || !disjoint(work, bwork, P, bp) ||
+      !disjoint(work, bwork, W, bw))
+    return fail(GW_ERR_ARG, "the workspace or V overlaps another operand");
+  if (P == W ? pt != wt : !disjoint(P, bp, W, bw))
+    return fail(GW_ERR_ARG, "P and W must be the same tensor of one dtype, or disjoint");
+  if (info && (!disjoint(info, 4, work, bwork) || !disjoint(info, 4, W, bw)))
+    return fail(GW_ERR_ARG, "info overlaps an operand");
+  hipStream_t s = (hipStream_t)stream;
+  const long long per = (long long)np * np;
+  double2* Vinv = static_cast<double2*>(work);
+  double2* Mw = Vinv + (long long)n_k * per;
+  double2* Dinv = Mw + chunk * per;
+  if (info) hipLaunchKernelGGL(dy_zero_info, dim3(1), dim3(64), 0, s, info);
+  // V^-1 for every q (flag -(q + 1) on a non-positive pivot)
+  hipLaunchKernelGGL(dy_load<double2>, dim3(grid_elems(per), n_k), dim3(256), 0, s, Vinv, per, np, n, 0,
+                     (const double2*)V, (const double2*)nullptr, 0LL, n_k);
+  gw_status st = gj_invert(Vinv, Dinv, n_k, np, info, 0, -1, s);
+  if (st != GW_OK) return st;
+  for (long long g0 = 0; g0 < total; g0 += chunk) {
+    const int cnt = (int)(total - g0 < chunk ? total - g0 : chunk);
+    if (pt == GW_C128)
+      hipLaunchKernelGGL(dy_load<double2>, dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n, 1,
+                         (const double2*)Vinv, (const double2*)P, g0, n_k);
+    else
+      hipLaunchKernelGGL(dy_load<float2>, dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n, 1,
+                         (const double2*)Vinv, (const float2*)P, g0, n_k);
+    st = gj_invert(Mw, Dinv, cnt, np, info, (int)g0, 1, s);
+    if (st != GW_OK) return st;
+    if (wt == GW_C128)
+      hipLaunchKernelGGL(dy_store<double2>, dim3(grid_elems((long long)n * n), cnt), dim3(256), 0, s, Mw, per, np,
+                         n, (const double2*)V, (double2*)W, g0, n_k);
+    else
+      hipLaunchKernelGGL(dy_store<float2>, dim3(grid_elems((long long)n * n), cnt), dim3(256), 0, s, Mw, per, np,
+                         n, (const double2*)V, (float2*)W, g0, n_k);
+  }
+  return check_launch("gw_screened_interaction");
+}
+
+gw_status gw_omega2tau_matrix(int n_tau, const double* tau, int n_omega, const double* omega, double* Ti) {
+  if (!tau || !omega || !Ti) return fail(GW_ERR_ARG, "NULL pointer");
+  if (n_omega != n_tau) return fail(GW_ERR_SHAPE, "the inverse needs n_omega == n_tau");
+  using cd = std::complex<double>;
+  const int n = n_tau;
+  std::vector<cd> a((size_t)n * n), x((size_t)n * n, cd(0, 0));
+  gw_status st = gw_tau2omega_matrix(n_tau, tau, n_omega, omega, reinterpret_cast<double*>(a.data()));
+  if (st != GW_OK) return st;
+  for (int i = 0; i < n; ++i) x[(size_t)i * n + i] = 1.0;
+  // Gauss-Jordan with partial pivoting on [a | x]
+  for (int p = 0; p < n; ++p) {
+    int best = p;
+    for (int r = p + 1; r < n; ++r)
+      if (std::abs(a[(size_t)r * n + p]) > std::abs(a[(size_t)best * n + p])) best = r;
+    if (!(std::abs(a[(size_t)best * n + p]) > 0.0)) return fail(GW_ERR_ARG, "tau -> omega matrix is singular");
+    if (best != p)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[(size_t)p * n + j], a[(size_t)best * n + j]);
+        std::swap(x[(size_t)p * n + j], x[(size_t)best * n + j]);
+      }
+    const cd inv = 1.0 / a[(size_t)p * n + p];
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)p * n + j] *= inv;
+      x[(size_t)p * n + j] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == p) continue;
+      const cd f = a[(size_t)r * n + p];
+      if (f == cd(0, 0)) continue;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)r * n + j] -= f * a[(size_t)p * n + j];
+        x[(size_t)r * n + j] -= f * x[(size_t)p * n + j];
+      }
+    }
+  }
+  std::memcpy(Ti, x.data(), x.size() * sizeof(cd));
+  return GW_OK;
+}
+
+}  // extern "C"

@@ -86,3 +86,19 @@ def test_inverse_needs_square():
     tau = np.linspace(0.0, 10.0, 8)
     with pytest.raises(ValueError):
         omega_to_tau_matrix(tau, oracle.bosonic_frequencies(6, 10.0))
+
+
+def test_library_inverse_matrix_matches_oracle():
+    # host helper of the library (no GPU needed) against numpy's inverse of the oracle matrix
+    g = pytest.importorskip("paper_1911_05633_amd")
+    beta, n = 60.0, 24
+    u = np.linspace(0.0, 1.0, n)
+    tau = beta * (0.5 - 0.5 * np.cos(np.pi * u))
+    for om in (oracle.bosonic_frequencies(n, beta), oracle.fermionic_frequencies(n, beta)):
+        Ti = g.gw_omega2tau_matrix(tau, om)
+        ref = omega_to_tau_matrix(tau, om)
+        # two inverses of the same matrix agree to about cond(T) * eps
+        kappa = np.linalg.cond(oracle.filon_matrix(tau, om))
+        assert np.linalg.norm(Ti - ref, 2) < 1e-14 * kappa * np.linalg.norm(ref, 2)
+    with pytest.raises(g.GWError):
+        g.gw_omega2tau_matrix(tau, oracle.bosonic_frequencies(n - 1, beta))

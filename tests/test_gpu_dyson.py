@@ -1,0 +1,148 @@
+"""GPU parity of the screened interaction, Eq. (2), against the oracle.
+
+gw_screened_interaction must give W~(q, nu) = (I - V P)^-1 V - V for every (q, nu) of seeded
+inputs: V Hermitian positive definite per q, P = -s_nu X_q X_q^H / n Hermitian negative
+semidefinite.  Cases: one 64-block (n = 32, padded), three blocks with a ragged tail (n = 150),
+and the 8-atom Si cell's n = 480 with 64 q points (sampled (q, nu) pairs against the oracle,
+Hermiticity of every output).  Bars: 1e-10 normwise relative for complex128 storage (FP64
+elimination; cond(V^-1 - P) is below 1e2 here), 2e-6 for complex64 P and W.  In-place use and
+a one-matrix workspace must give bit-identical results; pivots that are not positive must be
+reported through info; bad arguments are errors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthcell as sc
+
+pytestmark = pytest.mark.gpu
+
+
+def _cell(name):
+    import paper_1911_05633_amd as g
+    if name == "si8":
+        spec = sc.config(2)
+        return g.Cell.from_spec(spec, sc.coefficients(spec))
+    n_atoms, n_pb, mesh = {"one_block": (1, 32, (2, 2, 2)), "ragged": (3, 50, (2, 1, 1))}[name]
+    C = np.zeros((n_pb, 2, 2))
+    C[:, 0, 0] = 1.0
+    C[:, 1, 1] = 0.5
+    C[:, 0, 1] = C[:, 1, 0] = 0.25
+    return g.Cell([0] * n_atoms, [2], [n_pb], [C], mesh, 4, 10.0)
+
+
+def _inputs(cell, n_omega, seed):
+    V, X, s = sc.dyson_inputs(cell.N_R, cell.N_pb, n_omega, seed)
+    XX = X @ np.conj(np.swapaxes(X, -1, -2)) / cell.N_pb
+    P = -s[:, None, None, None] * XX[None]
+    return V, P
+
+
+def _run(cell, V, P, pdt="c128", wdt="c128", chunk=None, in_place=False, info=None):
+    import torch
+    import paper_1911_05633_amd as g
+    tp = torch.complex128 if pdt == "c128" else torch.complex64
+    tw = torch.complex128 if wdt == "c128" else torch.complex64
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    Pd = torch.from_numpy(np.ascontiguousarray(P)).to(tp).cuda()
+    Wd = Pd if in_place else torch.empty(Pd.shape, dtype=tw, device="cuda")
+    total = P.shape[0] * P.shape[1]
+    nb = g.gw_screened_interaction_workspace(cell, total if chunk is None else chunk)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    g.gw_screened_interaction(cell, Vd, Pd, Wd, work, info=info)
+    torch.cuda.synchronize()
+    return Wd.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name", ["one_block", "ragged"])
+def test_matches_oracle(name):
+    print(f"[dyson] {name} c128", flush=True)
+    cell = _cell(name)
+    V, P = _inputs(cell, 3, 1)
+    W = _run(cell, V, P)
+    ref = oracle.screened_interaction(V, P)
+    assert _rel(W, ref) < 1e-10
+
+
+def test_si8_sampled():
+    import torch
+    print("[dyson] si8 n=480, 64 q, 2 nu", flush=True)
+    cell = _cell("si8")
+    V, P = _inputs(cell, 2, 2)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    W = _run(cell, V, P, info=info)
+    assert int(info.item()) == 0
+    for m, q in [(0, 0), (0, 17), (0, 63), (1, 5), (1, 40), (1, 63)]:
+        ref = oracle.screened_interaction(V[q:q + 1], P[m:m + 1, q:q + 1])[0, 0]
+        assert _rel(W[m, q], ref) < 1e-10, (m, q)
+    herm = np.max(np.abs(W - np.conj(np.swapaxes(W, -1, -2)))) / np.max(np.abs(W))
+    assert herm < 1e-10
+
+
+def test_complex64_storage():
+    print("[dyson] ragged c64", flush=True)
+    cell = _cell("ragged")
+    V, P = _inputs(cell, 3, 3)
+    P32 = P.astype(np.complex64)
+    W = _run(cell, V, P32, pdt="c64", wdt="c64")
+    ref = oracle.screened_interaction(V, P32.astype(np.complex128))
+    assert W.dtype == np.complex64 and _rel(W, ref) < 2e-6
+
+
+def test_in_place_and_one_matrix_workspace_are_identical():
+    print("[dyson] ragged in place / chunk 1", flush=True)
+    cell = _cell("ragged")
+    V, P = _inputs(cell, 3, 4)
+    a = _run(cell, V, P)
+    b = _run(cell, V, P, in_place=True)
+    c = _run(cell, V, P, chunk=1)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_non_positive_pivots_are_reported():
+    import torch
+    print("[dyson] info flags", flush=True)
+    cell = _cell("ragged")
+    V, P = _inputs(cell, 2, 5)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _run(cell, V, -40.0 * P, info=info)     # V^-1 - P indefinite: a (q, nu) matrix is flagged
+    code = int(info.item())
+    assert 1 <= code <= 2 * cell.N_R
+    Vbad = V.copy()
+    Vbad[1] = -np.eye(cell.N_pb)
+    _run(cell, Vbad, P, info=info)          # V(q = 1) not positive definite
+    assert int(info.item()) == -2
+    _run(cell, V, P, info=info)
+    assert int(info.item()) == 0
+
+
+def test_argument_errors():
+    import ctypes
+    import torch
+    import paper_1911_05633_amd as g
+    print("[dyson] argument errors", flush=True)
+    cell = _cell("one_block")
+    V, P = _inputs(cell, 2, 6)
+    Vd = torch.from_numpy(V).cuda()
+    Pd = torch.from_numpy(P).cuda()
+    Wd = torch.empty_like(Pd)
+    small = torch.empty(g.gw_screened_interaction_workspace(cell, 1) - 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(g.GWError):
+        g.gw_screened_interaction(cell, Vd, Pd, Wd, small)
+    work = torch.empty(g.gw_screened_interaction_workspace(cell, 4), dtype=torch.uint8, device="cuda")
+
+    def raw(w_ptr, p_type=g.GW_C128, w_type=g.GW_C128):
+        return g.lib.gw_screened_interaction(cell.handle, ctypes.c_void_p(Vd.data_ptr()),
+                                             ctypes.c_void_p(Pd.data_ptr()), p_type, ctypes.c_void_p(w_ptr), w_type,
+                                             2, ctypes.c_void_p(work.data_ptr()), work.numel(), None, None)
+
+    assert raw(Pd.data_ptr() + 16) == g.GW_ERR_ARG                 # W overlaps P without being P
+    assert raw(Pd.data_ptr(), g.GW_C128, g.GW_C64) == g.GW_ERR_ARG  # in place with two dtypes
+    assert raw(work.data_ptr()) == g.GW_ERR_ARG                     # W inside the workspace
+    assert raw(Vd.data_ptr()) == g.GW_ERR_ARG                       # W overlaps V
+    with pytest.raises(TypeError):
+        g.gw_screened_interaction(cell, Vd.to(torch.complex64), Pd, Wd, work)

@@ -352,6 +352,76 @@ def pairs_bench(args, torch, log):
     print(json.dumps(out), flush=True)
 
 
+def dyson_bench(args, torch, log):
+    """Screened interaction, Eq. (2): W~ = (V^-1 - P)^-1 - V for every (q, nu) of the 8-atom Si
+    cell (N_pb 480, 64 q, 32 nu) and, sampled, of the 72-atom cell (N_pb 4320, 8 q, 4 of its
+    48 nu).  Seeded inputs (synthcell.dyson_factors), products for V and P formed on the device
+    before timing.  Work: 8 N_pb^3 real flops per inversion (the N_k inversions of V included)."""
+    import oracle
+    import synthcell as sc
+    import paper_1911_05633_amd as g
+    rows = []
+    cpu = None
+    for cfg, n_nu, steps in ((2, None, args.steps), (3, 4, 1)):
+        spec = sc.config(cfg)
+        cell = g.Cell.from_spec(spec, sc.coefficients(spec))
+        n, nk = cell.N_pb, cell.N_R
+        n_nu = spec.n_tau if n_nu is None else n_nu
+        t0 = time.time()
+        B, X, s = sc.dyson_factors(nk, n, n_nu, cfg)
+        Bd = torch.from_numpy(B).cuda()
+        V = torch.matmul(Bd, Bd.conj().transpose(-1, -2).contiguous()) / n
+        V.diagonal(dim1=-2, dim2=-1).add_(0.5)
+        del Bd
+        Xd = torch.from_numpy(X).cuda()
+        XX = torch.matmul(Xd, Xd.conj().transpose(-1, -2).contiguous()) / n
+        del Xd
+        P = torch.empty((n_nu, nk, n, n), dtype=torch.complex128, device="cuda")
+        for m in range(n_nu):
+            torch.mul(XX, -float(s[m]), out=P[m])
+        W = torch.empty_like(P)
+        total = n_nu * nk
+        work = torch.empty(g.gw_screened_interaction_workspace(cell, total), dtype=torch.uint8, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        log(f"dyson {spec.name}: inputs in {time.time() - t0:.1f}s; {total} (q, nu) matrices of {n}")
+        g.gw_screened_interaction(cell, V, P, W, work, info=info)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record()
+            g.gw_screened_interaction(cell, V, P, W, work, info=info)
+            b.record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        flops = 8.0 * n ** 3 * (total + nk)
+        # sampled parity against the oracle
+        Vh = V.cpu().numpy()
+        err = 0.0
+        for m, q in ((0, 0), (n_nu - 1, nk - 1)):
+            ref = oracle.screened_interaction(Vh[q:q + 1], P[m:m + 1, q:q + 1].cpu().numpy())[0, 0]
+            got = W[m, q].cpu().numpy()
+            err = max(err, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+        if cfg == 2 and not args.no_cpu:
+            Ph = P[0:1, 0:2].cpu().numpy()
+            c0 = time.perf_counter()
+            oracle.screened_interaction(Vh[0:2], Ph)
+            secs = time.perf_counter() - c0
+            cpu = {"value": 8.0 * n ** 3 * 2 / secs / 1e9, "unit": "GFLOP/s", "cores": os.cpu_count(),
+                   "kind": "oracle", "sample": f"numpy LU solve of 2 (q, nu) systems of {n}: {secs:.2f} s"}
+        rows.append({"cell": spec.name, "N_pb": n, "N_k": nk, "n_nu": n_nu, "matrices": total,
+                     "ms": ms, "ms_per_matrix": ms / total, "gflops": flops / (ms * 1e-3) / 1e9,
+                     "frac_fp64_peak": flops / (ms * 1e-3) / PEAK["fp64"], "info": int(info.item()),
+                     "max_rel_err_sampled": err})
+        log(f"dyson {spec.name}: {ms:.2f} ms, {rows[-1]['gflops']:.0f} GFLOP/s, info {rows[-1]['info']}, "
+            f"sampled rel err {err:.2e}")
+        del V, XX, P, W, work
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "screened interaction (Eq. 2) GFLOP/s, FP64 blocked Gauss-Jordan",
+                      "unit": "GFLOP/s", "higher_is_better": True, "dtype": "f64", "rows": rows,
+                      "cpu_baseline": cpu}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +439,8 @@ def main():
                     help="only run one plain device copy of GIB GiB (counter reference) and exit")
     ap.add_argument("--pairs", action="store_true",
                     help="time the real-space cutoff path against the dense one on 8- to 72-atom cells and exit")
+    ap.add_argument("--dyson", action="store_true",
+                    help="time the screened interaction (Eq. 2) on the 8- and 72-atom cells and exit")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -392,6 +464,9 @@ def main():
         return
     if args.pairs:
         pairs_bench(args, torch, log)
+        return
+    if args.dyson:
+        dyson_bench(args, torch, log)
         return
     spec = sc.config(args.config)
     log(f"config {args.config}: {spec.name}, {spec.n_atoms} atoms, N_orb {spec.N_orb}, N_pb {spec.N_pb}, "

@@ -7,7 +7,9 @@
  * Sigma (Eq. (8), MT-MT) of Kutepov's O(N) self-consistent GW method, and the
  * lattice (k <-> R) and Matsubara (tau -> i omega) transforms that feed and
  * drain them (Sec. 2: the F^R_{rr'} storage, the R <-> k transforms whose
- * cost is proportional to the number of pairs).
+ * cost is proportional to the number of pairs), the real-space cutoff with
+ * distance-tiered product basis (Sec. 2, Figs. 1, 2), and the screened
+ * interaction W of Eq. (2) that links P to Sigma.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -196,15 +198,16 @@ gw_status gw_tau2omega_matrix(int n_tau, const double* tau, int n_omega, const d
  *   W~(q, nu) = (I - V(q) P(q, nu))^-1 V(q) - V(q) = (V(q)^-1 - P(q, nu))^-1 - V(q).
  *   V:  DEVICE complex128 [N_k][N_pb][N_pb], Hermitian positive definite (bare Coulomb);
  *   P:  DEVICE [n_omega][N_k][N_pb][N_pb] in p_type storage (the layout gw_drain leaves with
- *       basis 1); each P(q, nu) Hermitian negative semidefinite, as at bosonic Matsubara
- *       frequencies, so that V^-1 - P is Hermitian positive definite;
+ *       basis 1); the Hermitian part of each P(q, nu) negative semidefinite (as at bosonic
+ *       Matsubara frequencies), so that V^-1 - P has a positive definite Hermitian part: then
+ *       every leading block is invertible and every pivot has a positive real part;
  *   W:  DEVICE, P's shape, w_type storage; may be P itself when p_type == w_type, else disjoint;
  *   work, work_size: DEVICE scratch of at least gw_screened_interaction_workspace(cell, 1)
  *       bytes, owned by the caller and not retained; more lets more (q, nu) matrices be
  *       inverted per launch (up to the size for chunk = n_omega * N_k);
  *   info: NULL, or a DEVICE int set to 0, then to -(q + 1) if V(q) or to 1 + nu * N_k + q if
- *       V(q)^-1 - P(q, nu) met a pivot that is not a positive real (one such matrix is named;
- *       its output is then meaningless).  Read it after the stream completes.
+ *       V(q)^-1 - P(q, nu) met a pivot whose real part is not positive (one such matrix is
+ *       named; the outputs are then not to be trusted).  Read it after the stream completes.
  * Both inverses are blocked Gauss-Jordan eliminations without pivoting, in FP64, on the
  * matrices padded to a multiple of 64 with the identity.  Enqueued on `stream`. */
 gw_status gw_screened_interaction(const gw_cell* cell, const void* V, const void* P, gw_dtype p_type, void* W,

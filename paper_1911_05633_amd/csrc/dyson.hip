@@ -1,9 +1,10 @@
 // Screened interaction, Eq. (2): W = V + V P W at every (q, nu), returned as its screening
 // part W~ = W - V (the part Eq. (8) consumes; Sec. 2 splits W = V + W~).
 //
-// With V Hermitian positive definite and P(q, nu) Hermitian negative semidefinite (bosonic
-// Matsubara frequencies), W = (I - V P)^-1 V = (V^-1 - P)^-1 and V^-1 - P is Hermitian
-// positive definite, so both inverses are taken by Gauss-Jordan elimination without
+// With V Hermitian positive definite and the Hermitian part of P(q, nu) negative semidefinite
+// (bosonic Matsubara frequencies), W = (I - V P)^-1 V = (V^-1 - P)^-1 and V^-1 - P has a
+// positive definite Hermitian part, as do all its Schur complements: every pivot has a
+// positive real part, so both inverses are taken by Gauss-Jordan elimination without
 // pivoting, in FP64, blocked by 64:
 //   per block step k (K = the 64 indices of block k), on M in place:
 //     D = M[K,K]^-1                     (one workgroup per matrix, LDS)
@@ -87,7 +88,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // Inverse of the diagonal block of step k by in-place Gauss-Jordan; written to Dinv[c] and to
-// M[c][K,K].  A pivot that is not a positive real number flags the matrix in *info.
+// M[c][K,K].  A pivot whose real part is not positive flags the matrix in *info.
 __global__ __launch_bounds__(256) void dy_diag(double2* __restrict__ M, double2* __restrict__ Dinv, long long per,
                                                int np, int k, int* info, int code0, int sign) {
   __shared__ double2 D[kDB * kDS];

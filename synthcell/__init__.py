@@ -405,17 +405,23 @@ def random_complex(shape, seed: int, dtype=np.complex128) -> np.ndarray:
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
 
 
-def dyson_inputs(n_k: int, n: int, n_omega: int, seed: int, scale: float = 0.5):
-    """Seeded inputs for the screened-interaction step.
-
-    Returns V [n_k][n][n] = B_q B_q^H / n + 0.5 I (Hermitian positive definite, a stand-in for
-    the bare Coulomb matrix), X [n_k][n][n] (complex Gaussian) and s [n_omega] = scale / (1 + m):
-    the caller forms P(q, nu_m) = -s_m X_q X_q^H / n, Hermitian negative semidefinite and
-    decaying over the frequency index, as a polarizability at bosonic frequencies does."""
+def dyson_factors(n_k: int, n: int, n_omega: int, seed: int, scale: float = 0.5):
+    """Seeded raw factors of the screened-interaction inputs: complex Gaussian B, X [n_k][n][n]
+    and s [n_omega] = scale / (1 + m).  With them V(q) = B_q B_q^H / n + 0.5 I (Hermitian
+    positive definite, a stand-in for the bare Coulomb matrix) and P(q, nu_m) =
+    -s_m X_q X_q^H / n (Hermitian negative semidefinite and decaying over the frequency index,
+    as a polarizability at bosonic frequencies is)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([ROOT_SEED, 71, seed])))
     B = rng.standard_normal((n_k, n, n)) + 1j * rng.standard_normal((n_k, n, n))
-    V = B @ np.conj(np.swapaxes(B, -1, -2)) / n
-    V[:, np.arange(n), np.arange(n)] += 0.5
     X = rng.standard_normal((n_k, n, n)) + 1j * rng.standard_normal((n_k, n, n))
     s = scale / (1.0 + np.arange(n_omega, dtype=np.float64))
+    return B, X, s
+
+
+def dyson_inputs(n_k: int, n: int, n_omega: int, seed: int, scale: float = 0.5):
+    """V [n_k][n][n], X [n_k][n][n] and s [n_omega] of dyson_factors, with V formed on the host
+    (small cases)."""
+    B, X, s = dyson_factors(n_k, n, n_omega, seed, scale)
+    V = B @ np.conj(np.swapaxes(B, -1, -2)) / n
+    V[:, np.arange(n), np.arange(n)] += 0.5
     return V, X, s

@@ -146,3 +146,43 @@ def test_argument_errors():
     assert raw(Vd.data_ptr()) == g.GW_ERR_ARG                       # W overlaps V
     with pytest.raises(TypeError):
         g.gw_screened_interaction(cell, Vd.to(torch.complex64), Pd, Wd, work)
+
+
+def test_closed_loop_p_w_sigma_fp64():
+    """G(k, tau) -> P -> P(q, i nu) -> W~(q, i nu) -> W~(q, tau) -> W~^R(tau) -> Sigma, all on the
+    GPU, against the same chain in the oracle (tiny cell).  P(q, i nu) of this chain has a negative
+    semidefinite Hermitian part, so the elimination meets only pivots with positive real part."""
+    import torch
+    import paper_1911_05633_amd as g
+    from tests import cells
+    print("[dyson] closed loop P -> W -> Sigma (tiny)", flush=True)
+    spec = cells.tiny(complex_hopping=True)
+    hop, b, Gk_h, C = cells.inputs(spec)
+    cell = g.Cell.from_spec(spec, C)
+    V = sc.dyson_inputs(spec.N_R, spec.N_pb, 1, 9)[0]
+    tau = sc.tau_grid(spec)
+    nu = g.matsubara(spec.n_tau, spec.beta, "bosonic")
+    Gk = torch.from_numpy(Gk_h).cuda()
+    GR = torch.empty_like(Gk)
+    g.gw_fourier_k2r(cell, Gk, GR, basis=0)
+    P = torch.empty((spec.n_tau, spec.N_R, spec.N_pb, spec.N_pb), dtype=torch.complex128, device="cuda")
+    g.gw_polarizability(cell, GR, P, spec.spin)
+    g.gw_drain(cell, torch.from_numpy(g.gw_tau2omega_matrix(tau, nu)).cuda(), P, P, basis=1, parity=1)
+    work = torch.empty(g.gw_screened_interaction_workspace(cell, spec.n_tau * spec.N_R), dtype=torch.uint8,
+                       device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g.gw_screened_interaction(cell, torch.from_numpy(V).cuda(), P, P, work, info=info)
+    g.gw_tau2omega(cell, torch.from_numpy(g.gw_omega2tau_matrix(tau, nu)).cuda(), P, P, basis=1, parity=0)
+    g.gw_fourier_k2r(cell, P, P, basis=1)
+    S = torch.empty((spec.n_tau, spec.N_R, spec.N_orb, spec.N_orb), dtype=torch.complex128, device="cuda")
+    g.gw_self_energy(cell, GR, P, S)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    om = oracle.bosonic_frequencies(spec.n_tau, spec.beta)
+    Pq = oracle.polarizability_q(Gk_h, spec, C, spec.spin)
+    Pw = oracle.apply_tau_to_omega(oracle.filon_matrix(tau, om), Pq)
+    Ww = oracle.screened_interaction(V, Pw)
+    Wt = oracle.apply_tau_to_omega(oracle.omega_to_tau_matrix(tau, om), Ww)
+    WR = oracle.k_to_r(Wt, spec.mesh)
+    S_ref = oracle.self_energy_r(oracle.k_to_r(Gk_h, spec.mesh), WR, spec, C)
+    assert _rel(S.cpu().numpy(), S_ref) < 1e-9

@@ -17,7 +17,8 @@ It computes, slowly and by the plain definitions of Kutepov's paper:
 * the electron count from G(R = 0, beta^-);
 * the real-space cutoff and distance tiers of the product basis (Sec. 2, Figs. 1, 2);
 * the screened interaction W~ = W - V from Eq. (2), and the inverse of the tau -> Matsubara
-  matrix.
+  matrix;
+* the static (exchange) self-energy: Eq. (8) with W~ -> V and G(tau) -> -G(beta).
 
 Conventions (the paper leaves them open; the readings are the same as the
 product library's documented ones):
@@ -43,3 +44,4 @@ from .density import electron_count  # noqa: F401
 from . import bruteforce  # noqa: F401
 from .cutoff import plan_pairs, polarizability_r_block_cut, self_energy_r_block_cut  # noqa: F401
 from .dyson import screened_interaction, omega_to_tau_matrix  # noqa: F401
+from .exchange import exchange_r, exchange_k  # noqa: F401

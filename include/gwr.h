@@ -192,6 +192,16 @@ gw_status gw_self_energy_pairs(const gw_cell* cell, const void* GR, const void* 
 gw_status gw_tau2omega_matrix(int n_tau, const double* tau, int n_omega, const double* omega,
                               double* T_host);
 
+/* Static (exchange) part of the self-energy (Sec. 2: the Eq. (8) expression with W~(tau)
+ * replaced by the bare V and G(tau) by -G(beta)):
+ *   Sigma_x^R_ab = + sum_{a',I in A; b',J in B} C^I_aa' G^R_a'b'(beta^-) V^R_IJ C^J_bb'
+ * GR: [n_tau][N_R][N_orb][N_orb] as for gw_self_energy; only the last time point (beta^-) is read.
+ * VR: [N_R][N_pb][N_pb] bare interaction in real space, same storage as GR (complex128 for
+ *     GW_FP64, complex64 otherwise).  Sigma_x: complex128 [N_R][N_orb][N_orb], not overlapping
+ *     the inputs.  Runs the self-energy kernels of the precision on that one time slice. */
+gw_status gw_exchange(const gw_cell* cell, const void* GR, const void* VR, void* Sigma_x, gw_precision prec,
+                      void* stream);
+
 /* Screened interaction, Eq. (2): at every momentum q and bosonic frequency nu the solution of
  * W = V + V P W, returned as its screening part W~ = W - V (Sec. 2 splits W = V + W~; W~ is
  * what Eq. (8) takes):

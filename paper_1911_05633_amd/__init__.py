@@ -43,6 +43,7 @@ SIGNATURES = {
     "gw_cell_pairs": (_c_int, [_vp, ctypes.POINTER(ctypes.c_longlong), _ip, ctypes.c_longlong]),
     "gw_polarizability_pairs": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
     "gw_self_energy_pairs": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
+    "gw_exchange": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_screened_interaction": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_int, _c_int, _vp, ctypes.c_size_t, _vp, _vp]),
     "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "gw_omega2tau_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
@@ -280,6 +281,18 @@ def gw_tau2omega_matrix(tau, omega):
     _check(lib.gw_tau2omega_matrix(len(tau), tau.ctypes.data_as(_dp), len(omega), omega.ctypes.data_as(_dp),
                                    out.ctypes.data_as(_dp)), "gw_tau2omega_matrix")
     return out
+
+
+def gw_exchange(cell, GR, VR, Sigma_x, prec=None):
+    """Static self-energy Sigma_x^R = + C G^R(beta^-) V^R C (Sigma_x: complex128 [N_R][N_orb][N_orb])."""
+    p = _prec(prec, GR)
+    want = GW_C128 if p == GW_FP64 else GW_C64
+    if _dtype_code(GR) != want or _dtype_code(VR) != want:
+        raise TypeError("GR and VR must be complex128 for fp64 and complex64 otherwise")
+    if _dtype_code(Sigma_x) != GW_C128:
+        raise TypeError("Sigma_x is always complex128")
+    _check(lib.gw_exchange(cell.handle, _ptr(GR, cell.elems(0), "GR"), _ptr(VR, cell.elems(1, 1), "VR"),
+                           _ptr(Sigma_x, cell.elems(0, 1), "Sigma_x"), p, _stream()), "gw_exchange")
 
 
 def gw_screened_interaction_workspace(cell, chunk=1):

@@ -18,7 +18,8 @@ It computes, slowly and by the plain definitions of Kutepov's paper:
 * the real-space cutoff and distance tiers of the product basis (Sec. 2, Figs. 1, 2);
 * the screened interaction W~ = W - V from Eq. (2), and the inverse of the tau -> Matsubara
   matrix;
-* the static (exchange) self-energy: Eq. (8) with W~ -> V and G(tau) -> -G(beta).
+* the static (exchange) self-energy: Eq. (8) with W~ -> V and G(tau) -> -G(beta);
+* the Dyson equation for G, Eq. (4).
 
 Conventions (the paper leaves them open; the readings are the same as the
 product library's documented ones):
@@ -45,3 +46,4 @@ from . import bruteforce  # noqa: F401
 from .cutoff import plan_pairs, polarizability_r_block_cut, self_energy_r_block_cut  # noqa: F401
 from .dyson import screened_interaction, omega_to_tau_matrix  # noqa: F401
 from .exchange import exchange_r, exchange_k  # noqa: F401
+from .green import green_dyson  # noqa: F401

@@ -228,6 +228,27 @@ gw_status gw_screened_interaction(const gw_cell* cell, const void* V, const void
  * 16 * (Np^2 * (N_k + chunk) + 4096 * max(N_k, chunk)), Np = N_pb rounded up to 64. */
 gw_status gw_screened_interaction_workspace(const gw_cell* cell, int chunk, size_t* bytes);
 
+/* Dyson equation for the Green's function, Eq. (4), with the Hartree-level G0^-1 = (i w + mu) - H:
+ *   G(k, i w_m) = [(i w_m + mu) I - H(k) - Sigma_x(k) - Sigma(k, i w_m)]^-1,
+ * at the first n_omega fermionic Matsubara frequencies w_m = (2 m + 1) pi / beta of the cell.
+ *   Hk:      DEVICE complex128 [N_k][N_orb][N_orb] (one-electron Hamiltonian on the k mesh);
+ *   Sigma:   DEVICE complex128 [n_omega][N_k][N_orb][N_orb] (the layout gw_drain leaves with
+ *            basis 0), or NULL for none;  Sigma_x: DEVICE complex128 [N_k][N_orb][N_orb] or NULL;
+ *   G:       DEVICE complex128 [n_omega][N_k][N_orb][N_orb]; may be Sigma itself, else disjoint;
+ *   work:    DEVICE scratch of at least gw_green_dyson_workspace(cell, 1) bytes (more inverts
+ *            more matrices per launch);
+ *   info:    NULL or a DEVICE int: 0, or 1 + m * N_k + k of a matrix that met a pivot of
+ *            -i A with non-positive real part (see below).
+ * The inverse is the blocked FP64 Gauss-Jordan elimination of gw_screened_interaction applied
+ * to -i A, whose Hermitian part w_m I - (Sigma - Sigma^H) / 2i is positive definite for a causal
+ * self-energy, so no pivoting is needed; G = -i (-i A)^-1. */
+gw_status gw_green_dyson(const gw_cell* cell, const void* Hk, double mu, int n_omega, const void* Sigma,
+                         const void* Sigma_x, void* G, void* work, size_t work_size, int* info, void* stream);
+
+/* Workspace bytes of gw_green_dyson for `chunk` matrices per launch:
+ * 16 * chunk * (No^2 + 4096), No = N_orb rounded up to 64. */
+gw_status gw_green_dyson_workspace(const gw_cell* cell, int chunk, size_t* bytes);
+
 /* Host helper: the inverse of gw_tau2omega_matrix(n_tau, tau, n_omega, omega) (needs
  * n_omega == n_tau), FP64 Gauss-Jordan with partial pivoting.  With it, gw_tau2omega (parity
  * 0, n_omega = n_tau) takes frequency samples back to the tau samples of the piecewise-linear

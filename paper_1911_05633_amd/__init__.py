@@ -46,6 +46,8 @@ SIGNATURES = {
     "gw_exchange": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_screened_interaction": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_int, _c_int, _vp, ctypes.c_size_t, _vp, _vp]),
     "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "gw_green_dyson": (_c_int, [_vp, _vp, _c_double, _c_int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
+    "gw_green_dyson_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "gw_omega2tau_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
     "gw_status_string": (ctypes.c_char_p, [_c_int]),
     "gw_last_error": (ctypes.c_char_p, []),
@@ -327,6 +329,38 @@ def gw_screened_interaction(cell, V, P, W, work, info=None):
                                        _ptr(W, P.numel(), "W"), _dtype_code(W), n_omega,
                                        ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size(), ip,
                                        _stream()), "gw_screened_interaction")
+
+
+def gw_green_dyson_workspace(cell, chunk=1):
+    """Workspace bytes of gw_green_dyson for `chunk` (k, w) matrices per launch."""
+    b = ctypes.c_size_t()
+    _check(lib.gw_green_dyson_workspace(cell.handle, int(chunk), ctypes.byref(b)), "gw_green_dyson_workspace")
+    return b.value
+
+
+def gw_green_dyson(cell, Hk, mu, G, work, Sigma=None, Sigma_x=None, info=None):
+    """G(k, i w_m) = [(i w_m + mu) - H(k) - Sigma_x(k) - Sigma(k, i w_m)]^-1; G: complex128
+    [n_omega][N_k][N_orb][N_orb] (n_omega taken from its size)."""
+    torch = _torch()
+    per = cell.N_R * cell.N_orb * cell.N_orb
+    if G.numel() % per or G.numel() == 0:
+        raise ValueError("G must hold n_omega * N_k * N_orb^2 elements")
+    n_omega = G.numel() // per
+    for t, name in ((Hk, "Hk"), (G, "G"), (Sigma, "Sigma"), (Sigma_x, "Sigma_x")):
+        if t is not None and t.dtype != torch.complex128:
+            raise TypeError(f"{name} must be complex128")
+    if not work.is_cuda or not work.is_contiguous():
+        raise ValueError("work must be a contiguous device tensor")
+    ip = None
+    if info is not None:
+        if info.dtype != torch.int32 or info.numel() != 1:
+            raise ValueError("info must be a one-element int32 device tensor")
+        ip = _ptr(info, 1, "info")
+    _check(lib.gw_green_dyson(cell.handle, _ptr(Hk, per, "Hk"), float(mu), n_omega,
+                              None if Sigma is None else _ptr(Sigma, G.numel(), "Sigma"),
+                              None if Sigma_x is None else _ptr(Sigma_x, per, "Sigma_x"),
+                              _ptr(G, G.numel(), "G"), ctypes.c_void_p(work.data_ptr()),
+                              work.numel() * work.element_size(), ip, _stream()), "gw_green_dyson")
 
 
 def gw_omega2tau_matrix(tau, omega):

@@ -83,6 +83,59 @@ __global__ __launch_bounds__(256) void dy_store(const double2* __restrict__ M, l
   }
 }
 
+// Green's function, Eq. (4): M[c] = -i A with A = (i w_m + mu) I - H(k) - Sigma_x(k) - Sigma(m, k),
+// g = g0 + c = m N_k + k, w_m = (2 m + 1) pi / beta; identity beyond n.  -i A has the Hermitian
+// part w_m I - (Sigma - Sigma^H) / 2i, positive definite for w_m > 0 and a causal Sigma.
+__global__ __launch_bounds__(256) void dy_load_green(double2* __restrict__ M, long long per, int np, int n,
+                                                     const double2* __restrict__ H, const double2* __restrict__ Sx,
+                                                     const double2* __restrict__ S, double mu, double beta,
+                                                     long long g0, int n_k) {
+  const int c = blockIdx.y;
+  const long long g = g0 + c;
+  const int k = (int)(g % n_k), m = (int)(g / n_k);
+  const double w = (2.0 * m + 1.0) * M_PI / beta;
+  double2* Mc = M + (long long)c * per;
+  const long long nn = (long long)np * np;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / np), j = (int)(e - (long long)i * np);
+    double2 v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    if (i < n && j < n) {
+      const long long o = (long long)i * n + j;
+      double2 a = H[(long long)k * n * n + o];
+      a = make_double2(-a.x, -a.y);
+      if (i == j) {
+        a.x += mu;
+        a.y += w;
+      }
+      if (Sx) {
+        const double2 x = Sx[(long long)k * n * n + o];
+        a.x -= x.x;
+        a.y -= x.y;
+      }
+      if (S) {
+        const double2 x = S[g * n * n + o];
+        a.x -= x.x;
+        a.y -= x.y;
+      }
+      v = make_double2(a.y, -a.x);  // -i a
+    }
+    Mc[e] = v;
+  }
+}
+
+// G[g] = A^-1 = -i M^-1 on the n x n corner
+__global__ __launch_bounds__(256) void dy_store_green(const double2* __restrict__ M, long long per, int np, int n,
+                                                      double2* __restrict__ G, long long g0) {
+  const int c = blockIdx.y;
+  const long long g = g0 + c;
+  const long long nn = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+    const double2 a = M[(long long)c * per + (long long)i * np + j];
+    G[g * nn + e] = make_double2(a.y, -a.x);
+  }
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -255,6 +308,10 @@ size_t work_bytes(int n_k, int np, long long chunk) {
   return 16 * ((size_t)np * np * (size_t)(n_k + chunk) + (size_t)kDB * kDB * (size_t)nd);
 }
 
+size_t green_bytes(int np, long long chunk) {
+  return 16 * ((size_t)np * np * (size_t)chunk + (size_t)kDB * kDB * (size_t)chunk);
+}
+
 bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
   auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
   return !(x < y + nb && y < x + na);
@@ -334,6 +391,54 @@ gw_status gw_screened_interaction(const gw_cell* c, const void* V, const void* P
                          n, (const double2*)V, (float2*)W, g0, n_k);
   }
   return check_launch("gw_screened_interaction");
+}
+
+gw_status gw_green_dyson_workspace(const gw_cell* c, int chunk, size_t* bytes) {
+  if (!c || !bytes) return fail(GW_ERR_ARG, "NULL pointer");
+  if (chunk < 1) return fail(GW_ERR_ARG, "chunk must be >= 1");
+  *bytes = green_bytes(padded(c->N_orb), chunk);
+  return GW_OK;
+}
+
+gw_status gw_green_dyson(const gw_cell* c, const void* Hk, double mu, int n_omega, const void* Sigma,
+                         const void* Sigma_x, void* G, void* work, size_t work_size, int* info, void* stream) {
+  if (!c) return fail(GW_ERR_ARG, "cell is NULL");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(GW_ERR_HIP, "hipGetDevice failed");
+  if (cur != c->device) return fail(GW_ERR_ARG, "current device differs from the cell's device");
+  if (!Hk || !G || !work) return fail(GW_ERR_ARG, "NULL pointer");
+  if (n_omega < 1) return fail(GW_ERR_SHAPE, "n_omega must be >= 1");
+  if (!std::isfinite(mu)) return fail(GW_ERR_ARG, "mu must be finite");
+  const int n_k = c->N_R, n = c->N_orb, np = padded(n);
+  const long long total = (long long)n_omega * n_k;
+  long long chunk = (long long)(work_size / green_bytes(np, 1));
+  if (chunk < 1) return fail(GW_ERR_SHAPE, "workspace smaller than gw_green_dyson_workspace(cell, 1)");
+  if (chunk > total) chunk = total;
+  if (chunk > 65535) chunk = 65535;
+  const size_t nh = (size_t)n_k * n * n * 16, ng = (size_t)total * n * n * 16, bwork = green_bytes(np, chunk);
+  if (!disjoint(Hk, nh, G, ng) || (Sigma_x && !disjoint(Sigma_x, nh, G, ng)) || !disjoint(work, bwork, G, ng) ||
+      !disjoint(work, bwork, Hk, nh) || (Sigma && !disjoint(work, bwork, Sigma, ng)) ||
+      (Sigma_x && !disjoint(work, bwork, Sigma_x, nh)))
+    return fail(GW_ERR_ARG, "an operand overlaps G or the workspace");
+  if (Sigma && Sigma != G && !disjoint(Sigma, ng, G, ng))
+    return fail(GW_ERR_ARG, "Sigma and G must be the same tensor or disjoint");
+  if (info && (!disjoint(info, 4, work, bwork) || !disjoint(info, 4, G, ng)))
+    return fail(GW_ERR_ARG, "info overlaps an operand");
+  hipStream_t s = (hipStream_t)stream;
+  const long long per = (long long)np * np;
+  double2* Mw = static_cast<double2*>(work);
+  double2* Dinv = Mw + chunk * per;
+  if (info) hipLaunchKernelGGL(dy_zero_info, dim3(1), dim3(64), 0, s, info);
+  for (long long g0 = 0; g0 < total; g0 += chunk) {
+    const int cnt = (int)(total - g0 < chunk ? total - g0 : chunk);
+    hipLaunchKernelGGL(dy_load_green, dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n,
+                       (const double2*)Hk, (const double2*)Sigma_x, (const double2*)Sigma, mu, c->beta, g0, n_k);
+    gw_status st = gj_invert(Mw, Dinv, cnt, np, info, (int)g0, 1, s);
+    if (st != GW_OK) return st;
+    hipLaunchKernelGGL(dy_store_green, dim3(grid_elems((long long)n * n), cnt), dim3(256), 0, s, Mw, per, np, n,
+                       (double2*)G, g0);
+  }
+  return check_launch("gw_green_dyson");
 }
 
 gw_status gw_omega2tau_matrix(int n_tau, const double* tau, int n_omega, const double* omega, double* Ti) {

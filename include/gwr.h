@@ -249,6 +249,26 @@ gw_status gw_green_dyson(const gw_cell* cell, const void* Hk, double mu, int n_o
  * 16 * chunk * (No^2 + 4096), No = N_orb rounded up to 64. */
 gw_status gw_green_dyson_workspace(const gw_cell* cell, int chunk, size_t* bytes);
 
+/* Electron count (Sec. 4) from G at the first n_omega fermionic frequencies of the cell:
+ *   n = (g / N_k) sum_k [ N_orb / 2 + (2 / beta) ( sum_{m < n_omega} Re Tr G(k, i w_m) - c2(k) S ) ],
+ *   c2(k) = Re Tr (H(k) + Sigma_x(k)) - mu N_orb,  S = sum_{m >= n_omega} 1 / w_m^2,
+ * i.e. the symmetric Matsubara sum of G with its 1 / (i w) and 1 / (i w)^2 tails (coefficients I
+ * and H - mu + Sigma_x) summed in closed form.  G: DEVICE complex128 [n_omega][N_k][N_orb][N_orb]
+ * (gw_green_dyson's output at this mu); Hk, Sigma_x (or NULL) as for gw_green_dyson; one FP64
+ * value written to the DEVICE pointer n_dev. */
+gw_status gw_density_omega(const gw_cell* cell, const void* G, int n_omega, const void* Hk, const void* Sigma_x,
+                           double mu, double spin_factor, double* n_dev, void* stream);
+
+/* Chemical-potential update (Sec. 4): bisection on mu in [mu_lo, mu_hi] (the count must rise
+ * through n_target there, else GW_ERR_ARG) until the electron count of the Dyson solution
+ * (gw_green_dyson, then gw_density_omega) is within tol of n_target, or max_iter steps.  G (not
+ * Sigma), work and n_dev are the caller's scratch; on return G holds the solution at *mu_out and
+ * *n_out its count.  Synchronous: waits on `stream` once per step. */
+gw_status gw_update_mu(const gw_cell* cell, const void* Hk, const void* Sigma, const void* Sigma_x, int n_omega,
+                       double spin_factor, double n_target, double mu_lo, double mu_hi, double tol, int max_iter,
+                       void* G, void* work, size_t work_size, double* n_dev, double* mu_out, double* n_out,
+                       void* stream);
+
 /* Host helper: the inverse of gw_tau2omega_matrix(n_tau, tau, n_omega, omega) (needs
  * n_omega == n_tau), FP64 Gauss-Jordan with partial pivoting.  With it, gw_tau2omega (parity
  * 0, n_omega = n_tau) takes frequency samples back to the tau samples of the piecewise-linear

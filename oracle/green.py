@@ -8,9 +8,17 @@ frequency-dependent parts of the self-energy both included:
 
 The inverse is a library primitive (numpy.linalg.inv, LU with partial pivoting, FP64).
 
+The chemical-potential update (Sec. 4) bisects on mu: the electron count of the Dyson solution
+must match the target.  The count is the Matsubara sum of Tr G over the frequencies kept, with
+the 1 / (i w) and 1 / (i w)^2 tails of G summed in closed form (their coefficients are I and
+H - mu + Sigma_x).
+
 Parity status: pinned in the tests by the band form of G0 (eigenvectors of H(k), Sigma = 0), by
 the scalar form, by the Dyson identity G = G0 + G0 Sigma G with the band-form G0, by the
-high-frequency tail i w G -> I, and by the exact Matsubara transform of the band G(tau).
+high-frequency tail i w G -> I, and by the exact Matsubara transform of the band G(tau).  The
+count is pinned by the Fermi sum of the band energies for Sigma = 0 (to the truncation error of
+the third-order tail); the update by the count it reaches and by the band chemical potential for
+Sigma = 0.
 """
 import numpy as np
 
@@ -35,3 +43,52 @@ def green_dyson(Hk, mu, omegas, Sigma=None, Sigma_x=None):
                 A = A - Sigma[m, k]
             out[m, k] = np.linalg.inv(A)
     return out
+
+
+def tail_sum(n_omega, beta):
+    """sum over m >= n_omega of 1 / w_m^2, w_m = (2 m + 1) pi / beta (closed form pi^2 / 8 minus the head)."""
+    head = np.sum(1.0 / (2.0 * np.arange(n_omega) + 1.0) ** 2)
+    return (beta / np.pi) ** 2 * (np.pi ** 2 / 8.0 - head)
+
+
+def density_omega(G, Hk, mu, beta, g, Sigma_x=None):
+    """Electron count from G at the first n_omega fermionic frequencies.
+
+    n = (g / N_k) sum_k [ N_orb / 2 + (2 / beta) ( sum_{m < n_omega} Re Tr G(k, i w_m) - c2(k) S ) ],
+    c2(k) = Re Tr (H(k) + Sigma_x(k)) - mu N_orb, S = sum_{m >= n_omega} 1 / w_m^2: the symmetric
+    Matsubara sum of G plus its 1 / (i w) and 1 / (i w)^2 tails, whose coefficients are I and
+    H - mu + Sigma_x."""
+    G = np.asarray(G)
+    n_om, n_k, n, _ = G.shape
+    A = float(np.sum(np.real(np.einsum("mkaa->", G))))
+    B = float(np.real(np.einsum("kaa->", Hk))) - mu * n * n_k
+    if Sigma_x is not None:
+        B += float(np.real(np.einsum("kaa->", Sigma_x)))
+    return float(g / n_k * (n_k * n / 2.0 + 2.0 / beta * (A - B * tail_sum(n_om, beta))))
+
+
+def update_mu(Hk, beta, n_omega, g, n_target, mu_lo, mu_hi, tol, max_iter, Sigma=None, Sigma_x=None):
+    """Chemical potential by bisection on the electron count of the Dyson solution.
+
+    The count rises with mu; the bracket must hold the target.  Each step solves Eq. (4) at the
+    midpoint and evaluates the count there; it stops when the count is within tol of the target
+    or after max_iter steps.  Returns (mu, count at mu)."""
+    om = fermionic_points(n_omega, beta)
+
+    def count(mu):
+        return density_omega(green_dyson(Hk, mu, om, Sigma, Sigma_x), Hk, mu, beta, g, Sigma_x)
+
+    lo, hi = float(mu_lo), float(mu_hi)
+    if not (count(lo) <= n_target <= count(hi)):
+        raise ValueError("the bracket does not hold the target count")
+    mid, n_mid = lo, None
+    for _ in range(max_iter):
+        mid = 0.5 * (lo + hi)
+        n_mid = count(mid)
+        if abs(n_mid - n_target) <= tol:
+            break
+        if n_mid < n_target:
+            lo = mid
+        else:
+            hi = mid
+    return mid, n_mid

@@ -48,6 +48,9 @@ SIGNATURES = {
     "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "gw_green_dyson": (_c_int, [_vp, _vp, _c_double, _c_int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "gw_green_dyson_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "gw_density_omega": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _c_double, _c_double, _vp, _vp]),
+    "gw_update_mu": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_double, _c_double, _c_double, _c_double, _c_double,
+                              _c_int, _vp, _vp, ctypes.c_size_t, _vp, _dp, _dp, _vp]),
     "gw_omega2tau_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
     "gw_status_string": (ctypes.c_char_p, [_c_int]),
     "gw_last_error": (ctypes.c_char_p, []),
@@ -361,6 +364,31 @@ def gw_green_dyson(cell, Hk, mu, G, work, Sigma=None, Sigma_x=None, info=None):
                               None if Sigma_x is None else _ptr(Sigma_x, per, "Sigma_x"),
                               _ptr(G, G.numel(), "G"), ctypes.c_void_p(work.data_ptr()),
                               work.numel() * work.element_size(), ip, _stream()), "gw_green_dyson")
+
+
+def gw_density_omega(cell, G, Hk, mu, spin_factor, n_out, Sigma_x=None):
+    """Electron count of G at the first n_omega fermionic frequencies (written to n_out)."""
+    per = cell.N_R * cell.N_orb * cell.N_orb
+    n_omega = G.numel() // per
+    _check(lib.gw_density_omega(cell.handle, _ptr(G, n_omega * per, "G"), n_omega, _ptr(Hk, per, "Hk"),
+                                None if Sigma_x is None else _ptr(Sigma_x, per, "Sigma_x"), float(mu),
+                                float(spin_factor), _ptr(n_out, 1, "n_out"), _stream()), "gw_density_omega")
+
+
+def gw_update_mu(cell, Hk, G, work, n_dev, spin_factor, n_target, mu_lo, mu_hi, tol=1e-10, max_iter=100,
+                 Sigma=None, Sigma_x=None):
+    """Bisection on mu; returns (mu, count).  G: complex128 [n_omega][N_k][N_orb][N_orb] scratch that
+    ends holding the Dyson solution at mu."""
+    per = cell.N_R * cell.N_orb * cell.N_orb
+    n_omega = G.numel() // per
+    mu, n = ctypes.c_double(), ctypes.c_double()
+    _check(lib.gw_update_mu(cell.handle, _ptr(Hk, per, "Hk"), None if Sigma is None else _ptr(Sigma, G.numel(), "Sigma"),
+                            None if Sigma_x is None else _ptr(Sigma_x, per, "Sigma_x"), n_omega, float(spin_factor),
+                            float(n_target), float(mu_lo), float(mu_hi), float(tol), int(max_iter),
+                            _ptr(G, G.numel(), "G"), ctypes.c_void_p(work.data_ptr()),
+                            work.numel() * work.element_size(), _ptr(n_dev, 1, "n_dev"), ctypes.byref(mu),
+                            ctypes.byref(n), _stream()), "gw_update_mu")
+    return mu.value, n.value
 
 
 def gw_omega2tau_matrix(tau, omega):

@@ -136,6 +136,34 @@ __global__ __launch_bounds__(256) void dy_store_green(const double2* __restrict_
   }
 }
 
+// Electron count from G at the first n_om fermionic frequencies (one workgroup):
+// n = (g / N_k) [N_k N_orb / 2 + (2 / beta) (sum Re Tr G(k, i w_m) - S sum_k c2(k))],
+// c2(k) = Re Tr (H(k) + Sigma_x(k)) - mu N_orb, S = sum_{m >= n_om} 1 / w_m^2 (host, closed form).
+__global__ __launch_bounds__(256) void dy_count(const double2* __restrict__ G, const double2* __restrict__ H,
+                                                const double2* __restrict__ Sx, int n_om, int n_k, int n, double mu,
+                                                double beta, double tail, double g, double* __restrict__ n_dev) {
+  __shared__ double part[256];
+  double a = 0.0, b = 0.0;
+  const long long nn = (long long)n * n;
+  for (long long i = threadIdx.x; i < (long long)n_om * n_k * n; i += 256) {
+    const long long mk = i / n;
+    const int d = (int)(i - mk * n);
+    a += G[mk * nn + (long long)d * n + d].x;
+  }
+  for (long long i = threadIdx.x; i < (long long)n_k * n; i += 256) {
+    const long long k = i / n;
+    const int d = (int)(i - k * n);
+    b += H[k * nn + (long long)d * n + d].x - mu + (Sx ? Sx[k * nn + (long long)d * n + d].x : 0.0);
+  }
+  part[threadIdx.x] = a - tail * b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_dev = g / n_k * (0.5 * (double)n_k * n + 2.0 / beta * part[0]);
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -439,6 +467,67 @@ gw_status gw_green_dyson(const gw_cell* c, const void* Hk, double mu, int n_omeg
                        (double2*)G, g0);
   }
   return check_launch("gw_green_dyson");
+}
+
+static double tail_sum(int n_om, double beta) {
+  // sum over m >= n_om of 1 / w_m^2 = (beta / pi)^2 (pi^2 / 8 - sum_{m < n_om} 1 / (2m + 1)^2)
+  double head = 0.0;
+  for (int m = n_om - 1; m >= 0; --m) head += 1.0 / ((2.0 * m + 1.0) * (2.0 * m + 1.0));
+  return (beta / M_PI) * (beta / M_PI) * (M_PI * M_PI / 8.0 - head);
+}
+
+gw_status gw_density_omega(const gw_cell* c, const void* G, int n_omega, const void* Hk, const void* Sigma_x,
+                           double mu, double spin_factor, double* n_dev, void* stream) {
+  if (!c) return fail(GW_ERR_ARG, "cell is NULL");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(GW_ERR_HIP, "hipGetDevice failed");
+  if (cur != c->device) return fail(GW_ERR_ARG, "current device differs from the cell's device");
+  if (!G || !Hk || !n_dev) return fail(GW_ERR_ARG, "NULL pointer");
+  if (n_omega < 1) return fail(GW_ERR_SHAPE, "n_omega must be >= 1");
+  if (!std::isfinite(mu) || !std::isfinite(spin_factor)) return fail(GW_ERR_ARG, "mu and spin factor must be finite");
+  hipLaunchKernelGGL(dy_count, dim3(1), dim3(256), 0, (hipStream_t)stream, (const double2*)G, (const double2*)Hk,
+                     (const double2*)Sigma_x, n_omega, c->N_R, c->N_orb, mu, c->beta, tail_sum(n_omega, c->beta),
+                     spin_factor, n_dev);
+  return check_launch("gw_density_omega");
+}
+
+gw_status gw_update_mu(const gw_cell* c, const void* Hk, const void* Sigma, const void* Sigma_x, int n_omega,
+                       double spin_factor, double n_target, double mu_lo, double mu_hi, double tol, int max_iter,
+                       void* G, void* work, size_t work_size, double* n_dev, double* mu_out, double* n_out,
+                       void* stream) {
+  if (!c || !mu_out || !n_out || !n_dev) return fail(GW_ERR_ARG, "NULL pointer");
+  if (!(mu_lo < mu_hi) || !std::isfinite(mu_lo) || !std::isfinite(mu_hi) || !(tol > 0) || max_iter < 1 ||
+      !std::isfinite(n_target))
+    return fail(GW_ERR_ARG, "need finite mu_lo < mu_hi, tol > 0, max_iter >= 1");
+  if (Sigma && Sigma == G) return fail(GW_ERR_ARG, "G must not be Sigma: every step reads Sigma again");
+  hipStream_t s = (hipStream_t)stream;
+  auto count = [&](double mu, double* out) -> gw_status {
+    gw_status st = gw_green_dyson(c, Hk, mu, n_omega, Sigma, Sigma_x, G, work, work_size, nullptr, stream);
+    if (st != GW_OK) return st;
+    st = gw_density_omega(c, G, n_omega, Hk, Sigma_x, mu, spin_factor, n_dev, stream);
+    if (st != GW_OK) return st;
+    if (hipMemcpyAsync(out, n_dev, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(GW_ERR_HIP, "reading the electron count failed");
+    return GW_OK;
+  };
+  double lo = mu_lo, hi = mu_hi, n_lo = 0, n_hi = 0;
+  gw_status st = count(lo, &n_lo);
+  if (st != GW_OK) return st;
+  st = count(hi, &n_hi);
+  if (st != GW_OK) return st;
+  if (!(n_lo <= n_target && n_target <= n_hi)) return fail(GW_ERR_ARG, "the bracket does not hold the target count");
+  double mid = lo, n_mid = n_lo;
+  for (int it = 0; it < max_iter; ++it) {
+    mid = 0.5 * (lo + hi);
+    st = count(mid, &n_mid);
+    if (st != GW_OK) return st;
+    if (std::fabs(n_mid - n_target) <= tol) break;
+    if (n_mid < n_target) lo = mid; else hi = mid;
+  }
+  *mu_out = mid;
+  *n_out = n_mid;
+  return GW_OK;
 }
 
 gw_status gw_omega2tau_matrix(int n_tau, const double* tau, int n_omega, const double* omega, double* Ti) {

@@ -142,3 +142,37 @@ def test_closed_loop_iteration_fp64():
     Sxo = oracle.r_to_k(oracle.exchange_r(GRo, VRh, spec, C)[None], spec.mesh)[0]
     Go = oracle.green_dyson(Hk, b.mu, omf, Sigma=Scw, Sigma_x=Sxo)
     assert _rel(Gn.cpu().numpy(), Go) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["tiny", "two_species"])
+def test_count_and_mu_update_match_oracle(name):
+    import torch
+    import paper_1911_05633_amd as g
+    from oracle.green import density_omega, update_mu
+    print(f"[green] count and mu update {name}", flush=True)
+    spec = CASES[name]()
+    hop, b, Gk, C = cells.inputs(spec)
+    Hk = sc.hamiltonian_k(spec, hop)
+    cell = g.Cell.from_spec(spec, C)
+    n_om = 32
+    S, Sx = _sigma(spec, n_om, 7)
+    om = fermionic_points(n_om, spec.beta)
+    mu = b.mu + 0.05
+    G = _run(cell, Hk, mu, n_om, S, Sx)
+    n_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    g.gw_density_omega(cell, dev(G), dev(Hk), mu, spec.spin, n_dev, Sigma_x=dev(Sx))
+    torch.cuda.synchronize()
+    ref = density_omega(oracle.green_dyson(Hk, mu, om, S, Sx), Hk, mu, spec.beta, spec.spin, Sx)
+    assert abs(float(n_dev.item()) - ref) < 1e-11 * abs(ref)
+    target = spec.spin * spec.N_orb / 2.0
+    Gs = torch.empty((n_om, spec.N_R, spec.N_orb, spec.N_orb), dtype=torch.complex128, device="cuda")
+    work = torch.empty(g.gw_green_dyson_workspace(cell, n_om * spec.N_R), dtype=torch.uint8, device="cuda")
+    mu_g, n_g = g.gw_update_mu(cell, dev(Hk), Gs, work, n_dev, spec.spin, target, b.mu - 1.0, b.mu + 1.0,
+                               tol=1e-10, max_iter=80, Sigma=dev(S), Sigma_x=dev(Sx))
+    mu_o, n_o = update_mu(Hk, spec.beta, n_om, spec.spin, target, b.mu - 1.0, b.mu + 1.0, 1e-10, 80, S, Sx)
+    assert abs(n_g - target) <= 1e-10 and abs(mu_g - mu_o) < 1e-8
+    assert _rel(Gs.cpu().numpy(), oracle.green_dyson(Hk, mu_g, om, S, Sx)) < 1e-10
+    with pytest.raises(g.GWError):
+        g.gw_update_mu(cell, dev(Hk), Gs, work, n_dev, spec.spin, target, b.mu + 5.0, b.mu + 6.0,
+                       Sigma=dev(S), Sigma_x=dev(Sx))

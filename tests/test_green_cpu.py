@@ -63,3 +63,31 @@ def test_matsubara_transform_of_band_green_function():
         exact = -(1.0 - f) * (np.exp((1j * w - x) * beta) - 1.0) / (1j * w - x)
         G = green_dyson(np.diag(x)[None].astype(complex), 0.0, np.array([w]))[0, 0]
         assert np.max(np.abs(np.diag(G) - exact)) < 1e-12 * np.max(np.abs(exact))
+
+
+def test_count_converges_to_fermi_sum():
+    from oracle.green import density_omega
+    spec = cells.tiny(complex_hopping=True)
+    hop, b, Gk, C = cells.inputs(spec)
+    Hk = sc.hamiltonian_k(spec, hop)
+    mu = b.mu + 0.3
+    exact = spec.spin * sc.fermi(b.eps - mu, spec.beta).sum() / spec.N_R
+    err = []
+    for n_om in (16, 64, 256):
+        G = green_dyson(Hk, mu, fermionic_points(n_om, spec.beta))
+        err.append(abs(density_omega(G, Hk, mu, spec.beta, spec.spin) - exact))
+    # the first dropped tail term falls as n_omega^-3: each fourfold step gains well over 20x
+    assert err[2] < 2e-5 * exact and err[1] < err[0] / 20 and err[2] < err[1] / 20
+
+
+def test_update_mu_reaches_band_chemical_potential():
+    import pytest
+    from oracle.green import update_mu
+    spec = cells.tiny(complex_hopping=True)
+    hop, b, Gk, C = cells.inputs(spec)
+    Hk = sc.hamiltonian_k(spec, hop)
+    target = spec.spin * spec.N_orb / 2.0
+    mu, n = update_mu(Hk, spec.beta, 64, spec.spin, target, b.mu - 1.0, b.mu + 1.0, 1e-10, 80)
+    assert abs(n - target) <= 1e-10 and abs(mu - b.mu) < 1e-4
+    with pytest.raises(ValueError):
+        update_mu(Hk, spec.beta, 64, spec.spin, target, b.mu + 0.5, b.mu + 1.0, 1e-10, 80)

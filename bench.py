@@ -417,9 +417,61 @@ def dyson_bench(args, torch, log):
             f"sampled rel err {err:.2e}")
         del V, XX, P, W, work
         torch.cuda.empty_cache()
+    green, exch = [], []
+    for cfg in (2, 3):
+        spec = sc.config(cfg)
+        C = sc.coefficients(spec)
+        cell = g.Cell.from_spec(spec, C)
+        n, nk, n_om = cell.N_orb, cell.N_R, spec.n_tau
+        b = sc.bands(spec)
+        Hk = torch.from_numpy(np.ascontiguousarray(sc.hamiltonian_k(spec, sc.hoppings(spec)))).cuda()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1000 + cfg)
+        X = torch.randn((nk, n, n), dtype=torch.complex128, device="cuda", generator=gen)
+        XX = torch.matmul(X, X.conj().transpose(-1, -2).contiguous()) / n
+        om = torch.tensor((2.0 * np.arange(n_om) + 1.0) * np.pi / spec.beta, dtype=torch.float64, device="cuda")
+        S = 0.2 * XX[None] / (1j * om[:, None, None, None] - 0.3)          # causal one-pole self-energy
+        G = torch.empty_like(S)
+        work = torch.empty(g.gw_green_dyson_workspace(cell, n_om * nk), dtype=torch.uint8, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        g.gw_green_dyson(cell, Hk, b.mu, G, work, Sigma=S, info=info)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        for a, e in ev:
+            a.record()
+            g.gw_green_dyson(cell, Hk, b.mu, G, work, Sigma=S, info=info)
+            e.record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(e) for a, e in ev]))
+        fl = 8.0 * n ** 3 * n_om * nk
+        green.append({"cell": spec.name, "N_orb": n, "N_k": nk, "n_omega": n_om, "matrices": n_om * nk, "ms": ms,
+                      "gflops": fl / (ms * 1e-3) / 1e9, "frac_fp64_peak": fl / (ms * 1e-3) / PEAK["fp64"],
+                      "info": int(info.item())})
+        log(f"green {spec.name}: {ms:.2f} ms for {n_om * nk} matrices of {n}, {green[-1]['gflops']:.0f} GFLOP/s")
+        del X, XX, S, G, work
+        # static exchange: the self-energy kernels on one time slice, per precision
+        for prec in ("fp64", "bf16x3"):
+            cdt = torch.complex128 if prec == "fp64" else torch.complex64
+            GR = torch.randn((spec.n_tau, nk, n, n), dtype=cdt, device="cuda", generator=gen)
+            VR = torch.randn((nk, cell.N_pb, cell.N_pb), dtype=cdt, device="cuda", generator=gen)
+            Sx = torch.empty((nk, n, n), dtype=torch.complex128, device="cuda")
+            g.gw_exchange(cell, GR, VR, Sx, prec=prec)
+            torch.cuda.synchronize()
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                g.gw_exchange(cell, GR, VR, Sx, prec=prec)
+            e.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(e) / 3
+            fs = pair_flops(spec)[1] * nk
+            exch.append({"cell": spec.name, "prec": prec, "ms": ms, "gflops": fs / (ms * 1e-3) / 1e9})
+            log(f"exchange {spec.name} {prec}: {ms:.3f} ms, {exch[-1]['gflops']:.0f} GFLOP/s")
+            del GR, VR, Sx
+        torch.cuda.empty_cache()
     print(json.dumps({"metric": "screened interaction (Eq. 2) GFLOP/s, FP64 blocked Gauss-Jordan",
                       "unit": "GFLOP/s", "higher_is_better": True, "dtype": "f64", "rows": rows,
-                      "cpu_baseline": cpu}))
+                      "green_dyson": green, "exchange": exch, "cpu_baseline": cpu}))
 
 
 def main():

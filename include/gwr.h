@@ -192,6 +192,29 @@ gw_status gw_self_energy_pairs(const gw_cell* cell, const void* GR, const void* 
 gw_status gw_tau2omega_matrix(int n_tau, const double* tau, int n_omega, const double* omega,
                               double* T_host);
 
+/* Interstitial-grid blocks of P, Eqs. (6), (7).  n_g real-space grid points per cell stand for
+ * the interstitial region; a grid point enters as one "orbital" (the value of G there) and one
+ * "product function" (the product of two G values there), so the MT coefficients remain only on
+ * the muffin-tin side.  Per (tau, R), row-major, in `type` storage (complex128 or complex64):
+ *   G_og [n_tau][N_R][N_orb][n_g] = G^R_{tL; r'},  G_go [n_tau][N_R][n_g][N_orb] = G^R_{r; tL},
+ *   G_gg [n_tau][N_R][n_g][n_g];
+ *   P_pg [n_tau][N_R][N_pb][n_g]: P^R_{tK; r'}(tau) = -g sum_{a,b in t} C^K_ab G^R_{a r'}(tau) G^{-R}_{r' b}(beta - tau)
+ *   P_gp [n_tau][N_R][n_g][N_pb]: P^R_{r; tK}(tau) = -g sum_{c,d in t} G^R_{r c}(tau) G^{-R}_{d r}(beta - tau) C^K_cd
+ *   P_gg [n_tau][N_R][n_g][n_g]:  P^R_{r r'}(tau) = -g G^R_{r r'}(tau) G^{-R}_{r' r}(beta - tau)
+ * (the second G read as in Eq. (5)).  FP64 arithmetic; outputs must not overlap inputs or each
+ * other.  Up to 8 species. */
+gw_status gw_polarizability_int(const gw_cell* cell, int n_g, const void* G_og, const void* G_go, const void* G_gg,
+                                void* P_pg, void* P_gp, void* P_gg, double spin_factor, gw_dtype type, void* stream);
+
+/* Interstitial-grid blocks of Sigma, Eqs. (9), (10), W at the same tau as G; W blocks laid out
+ * as the P blocks above, Sigma blocks as the G blocks but always complex128:
+ *   S_og[tL][r'] = -sum_{I, a' in t} C^I_{L a'} G^R_{a' r'}(tau) W^R_{I r'}(tau)
+ *   S_go[r][tL]  = -sum_{J, b' in t} G^R_{r b'}(tau) W^R_{r J}(tau) C^J_{L b'}
+ *   S_gg[r][r']  = -G^R_{r r'}(tau) W^R_{r r'}(tau). */
+gw_status gw_self_energy_int(const gw_cell* cell, int n_g, const void* G_og, const void* G_go, const void* G_gg,
+                             const void* W_pg, const void* W_gp, const void* W_gg, void* S_og, void* S_go,
+                             void* S_gg, gw_dtype type, void* stream);
+
 /* Static (exchange) part of the self-energy (Sec. 2: the Eq. (8) expression with W~(tau)
  * replaced by the bare V and G(tau) by -G(beta)):
  *   Sigma_x^R_ab = + sum_{a',I in A; b',J in B} C^I_aa' G^R_a'b'(beta^-) V^R_IJ C^J_bb'

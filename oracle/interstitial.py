@@ -45,19 +45,19 @@ def _assemble(oo_shape, og, go, gg):
     return X
 
 
-def polarizability_int(G_og, G_go, G_gg, spec, C, g):
-    """(P_pg, P_gp, P_gg) of Eqs. (6), (7) for every tau and R."""
+def polarizability_int(G_og, G_go, G_gg, spec, C, g, taus=None, Rs=None):
+    """(P_pg, P_gp, P_gg) of Eqs. (6), (7) at the given tau and R indices (default all)."""
     n_g = G_gg.shape[-1]
     ns, Cx = extended(spec, C, n_g)
-    P = polarizability_r(_assemble(None, G_og, G_go, G_gg), ns, Cx, g)
+    P = polarizability_r(_assemble(None, G_og, G_go, G_gg), ns, Cx, g, taus, Rs)
     Np = spec.N_pb
     return P[:, :, :Np, Np:], P[:, :, Np:, :Np], P[:, :, Np:, Np:]
 
 
-def self_energy_int(G_og, G_go, G_gg, W_pg, W_gp, W_gg, spec, C):
-    """(S_og, S_go, S_gg) of Eqs. (9), (10) for every tau and R."""
+def self_energy_int(G_og, G_go, G_gg, W_pg, W_gp, W_gg, spec, C, taus=None, Rs=None):
+    """(S_og, S_go, S_gg) of Eqs. (9), (10) at the given tau and R indices (default all)."""
     n_g = G_gg.shape[-1]
     ns, Cx = extended(spec, C, n_g)
-    S = self_energy_r(_assemble(None, G_og, G_go, G_gg), _assemble(None, W_pg, W_gp, W_gg), ns, Cx)
+    S = self_energy_r(_assemble(None, G_og, G_go, G_gg), _assemble(None, W_pg, W_gp, W_gg), ns, Cx, taus, Rs)
     No = spec.N_orb
     return S[:, :, :No, No:], S[:, :, No:, :No], S[:, :, No:, No:]

@@ -43,6 +43,8 @@ SIGNATURES = {
     "gw_cell_pairs": (_c_int, [_vp, ctypes.POINTER(ctypes.c_longlong), _ip, ctypes.c_longlong]),
     "gw_polarizability_pairs": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
     "gw_self_energy_pairs": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
+    "gw_polarizability_int": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _c_double, _c_int, _vp]),
+    "gw_self_energy_int": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_exchange": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_screened_interaction": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_int, _c_int, _vp, ctypes.c_size_t, _vp, _vp]),
     "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
@@ -286,6 +288,42 @@ def gw_tau2omega_matrix(tau, omega):
     _check(lib.gw_tau2omega_matrix(len(tau), tau.ctypes.data_as(_dp), len(omega), omega.ctypes.data_as(_dp),
                                    out.ctypes.data_as(_dp)), "gw_tau2omega_matrix")
     return out
+
+
+def _int_blocks(cell, n_g, tensors, rows, names):
+    bl = cell.n_tau * cell.N_R
+    code = _dtype_code(tensors[0])
+    ptrs = []
+    for t, r, name in zip(tensors, rows, names):
+        if _dtype_code(t) != code:
+            raise TypeError("all interstitial blocks must share one dtype")
+        ptrs.append(_ptr(t, bl * r * n_g, name))
+    return ptrs, code
+
+
+def gw_polarizability_int(cell, G_og, G_go, G_gg, P_pg, P_gp, P_gg, spin_factor=2.0):
+    """Interstitial blocks of P (Eqs. (6), (7)); n_g is read from G_gg's last axis."""
+    n_g = int(G_gg.shape[-1])
+    ptrs, code = _int_blocks(cell, n_g, [G_og, G_go, G_gg, P_pg, P_gp, P_gg],
+                             [cell.N_orb, cell.N_orb, n_g, cell.N_pb, cell.N_pb, n_g],
+                             ["G_og", "G_go", "G_gg", "P_pg", "P_gp", "P_gg"])
+    _check(lib.gw_polarizability_int(cell.handle, n_g, *ptrs, float(spin_factor), code, _stream()),
+           "gw_polarizability_int")
+
+
+def gw_self_energy_int(cell, G_og, G_go, G_gg, W_pg, W_gp, W_gg, S_og, S_go, S_gg):
+    """Interstitial blocks of Sigma (Eqs. (9), (10)); Sigma blocks complex128."""
+    n_g = int(G_gg.shape[-1])
+    ptrs, code = _int_blocks(cell, n_g, [G_og, G_go, G_gg, W_pg, W_gp, W_gg],
+                             [cell.N_orb, cell.N_orb, n_g, cell.N_pb, cell.N_pb, n_g],
+                             ["G_og", "G_go", "G_gg", "W_pg", "W_gp", "W_gg"])
+    bl = cell.n_tau * cell.N_R
+    outs = []
+    for t, r, name in zip([S_og, S_go, S_gg], [cell.N_orb, cell.N_orb, n_g], ["S_og", "S_go", "S_gg"]):
+        if _dtype_code(t) != GW_C128:
+            raise TypeError("Sigma blocks are complex128")
+        outs.append(_ptr(t, bl * r * n_g, name))
+    _check(lib.gw_self_energy_int(cell.handle, n_g, *ptrs, *outs, code, _stream()), "gw_self_energy_int")
 
 
 def gw_exchange(cell, GR, VR, Sigma_x, prec=None):

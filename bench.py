@@ -474,6 +474,53 @@ def dyson_bench(args, torch, log):
                       "green_dyson": green, "exchange": exch, "cpu_baseline": cpu}))
 
 
+def interstitial_bench(args, torch, log):
+    """Interstitial-grid blocks of P and Sigma (Eqs. (6), (7), (9), (10)) with n_g grid points per
+    cell, complex64 storage (the mixed path's), random seeded blocks on the device.  Per kernel:
+    HIP-event time, algorithmic HBM bytes (each block read or written once) and FP64 flops."""
+    import synthcell as sc
+    import paper_1911_05633_amd as g
+    rows = []
+    for cfg, n_g in ((2, 256), (3, 256)):
+        spec = sc.config(cfg)
+        cell = g.Cell.from_spec(spec, sc.coefficients(spec))
+        nt, nr, no, npb = spec.n_tau, spec.N_R, spec.N_orb, spec.N_pb
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(2000 + cfg)
+        rnd = lambda *sh: torch.randn(sh, dtype=torch.complex64, device="cuda", generator=gen)
+        G = [rnd(nt, nr, no, n_g), rnd(nt, nr, n_g, no), rnd(nt, nr, n_g, n_g)]
+        W = [rnd(nt, nr, npb, n_g), rnd(nt, nr, n_g, npb), rnd(nt, nr, n_g, n_g)]
+        P = [torch.empty_like(W[0]), torch.empty_like(W[1]), torch.empty_like(W[2])]
+        S = [torch.empty((nt, nr, no, n_g), dtype=torch.complex128, device="cuda"),
+             torch.empty((nt, nr, n_g, no), dtype=torch.complex128, device="cuda"),
+             torch.empty((nt, nr, n_g, n_g), dtype=torch.complex128, device="cuda")]
+        for name, fn in (("P_int", lambda: g.gw_polarizability_int(cell, *G, *P, spec.spin)),
+                         ("Sigma_int", lambda: g.gw_self_energy_int(cell, *G, *W, *S))):
+            fn()
+            torch.cuda.synchronize()
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            e.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(e)
+            bl = nt * nr
+            n2 = float((np.asarray(spec.atom_norb) ** 2 * np.asarray(spec.atom_npb)).sum())
+            if name == "P_int":
+                byts = bl * 8.0 * (2 * 2 * no * n_g + 2 * npb * n_g + 3 * n_g * n_g)
+                flops = bl * n_g * 2 * n2 * 4.0 + bl * n_g * n_g * 8.0
+            else:
+                byts = bl * (8.0 * (2 * no * n_g + 2 * npb * n_g + 2 * n_g * n_g) + 16.0 * (2 * no * n_g + n_g * n_g))
+                flops = bl * n_g * 2 * n2 * 8.0 + bl * n_g * n_g * 8.0
+            rows.append({"cell": spec.name, "n_g": n_g, "kernels": name, "ms": ms, "GB": byts / 1e9,
+                         "TB_per_s": byts / (ms * 1e-3) / 1e12, "TFLOP_per_s": flops / (ms * 1e-3) / 1e12})
+            log(f"{name} {spec.name} n_g={n_g}: {ms:.2f} ms, {rows[-1]['TB_per_s']:.2f} TB/s, "
+                f"{rows[-1]['TFLOP_per_s']:.1f} TFLOP/s")
+        del G, W, P, S
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "interstitial blocks (Eqs. 6, 7, 9, 10): HBM TB/s and FP64 TFLOP/s", "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,6 +540,8 @@ def main():
                     help="time the real-space cutoff path against the dense one on 8- to 72-atom cells and exit")
     ap.add_argument("--dyson", action="store_true",
                     help="time the screened interaction (Eq. 2) on the 8- and 72-atom cells and exit")
+    ap.add_argument("--interstitial", action="store_true",
+                    help="time the interstitial-grid blocks of P and Sigma and exit")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -519,6 +568,9 @@ def main():
         return
     if args.dyson:
         dyson_bench(args, torch, log)
+        return
+    if args.interstitial:
+        interstitial_bench(args, torch, log)
         return
     spec = sc.config(args.config)
     log(f"config {args.config}: {spec.name}, {spec.n_atoms} atoms, N_orb {spec.N_orb}, N_pb {spec.N_pb}, "

@@ -11,7 +11,8 @@
 namespace gwr {
 namespace {
 
-constexpr int kGT = 32;  // LDS transpose tile of the INT-INT polarizability
+constexpr int kGT = 32;    // LDS transpose tile of the INT-INT polarizability
+constexpr int kCS = 4096;  // doubles of coefficients staged in LDS per pass (whole rows C^K)
 
 __device__ __forceinline__ double2 ld(const double2* p) { return *p; }
 __device__ __forceinline__ double2 ld(const float2* p) {
@@ -35,15 +36,17 @@ struct IntArgs {
 };
 
 // MT-INT and INT-MT blocks of P (Eq. (6) and its mirror partner).  Thread: grid point r;
-// block: (r chunk, atom t, tau * NR + R).
+// block: (256-point chunk, atom t, tau * NR + R); the atom's coefficients pass through LDS a
+// few whole C^K at a time (every lane reads the same one: broadcast).
 //   MODE 0: P_pg[t K][r] = -g sum_ab C^K_ab G_og[tau][R][t a][r] G_go[tau'][-R][r][t b]
 //   MODE 1: P_gp[r][t K] = -g sum_cd G_go[tau][R][r][t c] G_og[tau'][-R][t d][r] C^K_cd
 template <class T, int MODE>
-__global__ __launch_bounds__(64) void p_mixed(const T* __restrict__ Gog, const T* __restrict__ Ggo, T* __restrict__ P,
-                                              double g, const IntArgs q) {
-  const int r = blockIdx.x * 64 + threadIdx.x, t = blockIdx.y;
+__global__ __launch_bounds__(256) void p_mixed(const T* __restrict__ Gog, const T* __restrict__ Ggo, T* __restrict__ P,
+                                               double g, const IntArgs q) {
+  __shared__ double Cs[kCS];
+  const int r = blockIdx.x * 256 + threadIdx.x, t = blockIdx.y;
   const int tau = blockIdx.z / q.NR, R = blockIdx.z - tau * q.NR;
-  if (r >= q.ng) return;
+  const bool on = r < q.ng;
   const int tm = q.n_tau - 1 - tau, mR = q.minusR[R];
   const int s = q.species[t], n = q.n[s], m = q.m[s], o = q.orb_off[t], pb = q.pb_off[t];
   const double* C = q.C[s];
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(64) void p_mixed(const T* __restrict__ Gog, const T
   double2 x[kMaxOrb], y[kMaxOrb];
 #pragma unroll
   for (int a = 0; a < kMaxOrb; ++a) {
-    if (a < n) {
+    if (on && a < n) {
       if (MODE == 0) {
         x[a] = ld(Gog + ((long long)tau * q.NR + R) * sl + (long long)(o + a) * q.ng + r);
         y[a] = ld(Ggo + ((long long)tm * q.NR + mR) * sl + (long long)r * q.No + o + a);
@@ -63,31 +66,40 @@ __global__ __launch_bounds__(64) void p_mixed(const T* __restrict__ Gog, const T
   }
   const long long pl = (long long)q.Np * q.ng;
   T* Pb = P + ((long long)tau * q.NR + R) * pl;
-  for (int K = 0; K < m; ++K) {
-    double2 acc = make_double2(0.0, 0.0);
-    const double* CK = C + (long long)K * n * n;
+  const int nn = n * n, rows = kCS / nn;
+  for (int K0 = 0; K0 < m; K0 += rows) {
+    const int nk = m - K0 < rows ? m - K0 : rows;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nk * nn; i += 256) Cs[i] = C[(long long)K0 * nn + i];
+    __syncthreads();
+    if (!on) continue;
+    for (int k = 0; k < nk; ++k) {
+      const double* CK = Cs + k * nn;
+      double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int a = 0; a < kMaxOrb; ++a) {
-      if (a < n) {
-        double2 row = make_double2(0.0, 0.0);
+      for (int a = 0; a < kMaxOrb; ++a) {
+        if (a < n) {
+          double2 row = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int b = 0; b < kMaxOrb; ++b) {
-          if (b < n) {
-            const double c = CK[a * n + b];
-            row.x += c * y[b].x;
-            row.y += c * y[b].y;
+          for (int b = 0; b < kMaxOrb; ++b) {
+            if (b < n) {
+              const double c = CK[a * n + b];
+              row.x += c * y[b].x;
+              row.y += c * y[b].y;
+            }
           }
+          const double2 v = cm(x[a], row);
+          acc.x += v.x;
+          acc.y += v.y;
         }
-        const double2 v = cm(x[a], row);
-        acc.x += v.x;
-        acc.y += v.y;
       }
+      const double2 out = make_double2(-g * acc.x, -g * acc.y);
+      const int K = K0 + k;
+      if (MODE == 0)
+        st(Pb + (long long)(pb + K) * q.ng + r, out);
+      else
+        st(Pb + (long long)r * q.Np + pb + K, out);
     }
-    const double2 out = make_double2(-g * acc.x, -g * acc.y);
-    if (MODE == 0)
-      st(Pb + (long long)(pb + K) * q.ng + r, out);
-    else
-      st(Pb + (long long)r * q.Np + pb + K, out);
   }
 }
 
@@ -95,11 +107,12 @@ __global__ __launch_bounds__(64) void p_mixed(const T* __restrict__ Gog, const T
 //   MODE 0: S_og[t L][r] = -sum_{I, a'} C^I_{L a'} G_og[t a'][r] W_pg[t I][r]
 //   MODE 1: S_go[r][t L] = -sum_{J, b'} G_go[r][t b'] W_gp[r][t J] C^J_{L b'}
 template <class T, int MODE>
-__global__ __launch_bounds__(64) void s_mixed(const T* __restrict__ Gx, const T* __restrict__ Wx,
-                                              double2* __restrict__ S, const IntArgs q) {
-  const int r = blockIdx.x * 64 + threadIdx.x, t = blockIdx.y;
+__global__ __launch_bounds__(256) void s_mixed(const T* __restrict__ Gx, const T* __restrict__ Wx,
+                                               double2* __restrict__ S, const IntArgs q) {
+  __shared__ double Cs[kCS];
+  const int r = blockIdx.x * 256 + threadIdx.x, t = blockIdx.y;
   const int tau = blockIdx.z / q.NR, R = blockIdx.z - tau * q.NR;
-  if (r >= q.ng) return;
+  const bool on = r < q.ng;
   const int s = q.species[t], n = q.n[s], m = q.m[s], o = q.orb_off[t], pb = q.pb_off[t];
   const double* C = q.C[s];
   const long long blk = (long long)tau * q.NR + R;
@@ -108,30 +121,40 @@ __global__ __launch_bounds__(64) void s_mixed(const T* __restrict__ Gx, const T*
 #pragma unroll
   for (int a = 0; a < kMaxOrb; ++a) {
     acc[a] = make_double2(0.0, 0.0);
-    if (a < n)
+    if (on && a < n)
       x[a] = MODE == 0 ? ld(Gx + blk * gl + (long long)(o + a) * q.ng + r) : ld(Gx + blk * gl + (long long)r * q.No + o + a);
   }
-  for (int I = 0; I < m; ++I) {
-    const double2 w = MODE == 0 ? ld(Wx + blk * wl + (long long)(pb + I) * q.ng + r) : ld(Wx + blk * wl + (long long)r * q.Np + pb + I);
-    const double* CI = C + (long long)I * n * n;
+  const int nn = n * n, rows = kCS / nn;
+  for (int I0 = 0; I0 < m; I0 += rows) {
+    const int nk = m - I0 < rows ? m - I0 : rows;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nk * nn; i += 256) Cs[i] = C[(long long)I0 * nn + i];
+    __syncthreads();
+    if (!on) continue;
+    for (int k = 0; k < nk; ++k) {
+      const int I = I0 + k;
+      const double2 w = MODE == 0 ? ld(Wx + blk * wl + (long long)(pb + I) * q.ng + r) : ld(Wx + blk * wl + (long long)r * q.Np + pb + I);
+      const double* CI = Cs + k * nn;
 #pragma unroll
-    for (int L = 0; L < kMaxOrb; ++L) {
-      if (L < n) {
-        double2 cx = make_double2(0.0, 0.0);
+      for (int L = 0; L < kMaxOrb; ++L) {
+        if (L < n) {
+          double2 cx = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int a = 0; a < kMaxOrb; ++a) {
-          if (a < n) {
-            const double c = CI[L * n + a];
-            cx.x += c * x[a].x;
-            cx.y += c * x[a].y;
+          for (int a = 0; a < kMaxOrb; ++a) {
+            if (a < n) {
+              const double c = CI[L * n + a];
+              cx.x += c * x[a].x;
+              cx.y += c * x[a].y;
+            }
           }
+          const double2 v = cm(cx, w);
+          acc[L].x += v.x;
+          acc[L].y += v.y;
         }
-        const double2 v = cm(cx, w);
-        acc[L].x += v.x;
-        acc[L].y += v.y;
       }
     }
   }
+  if (!on) return;
   double2* Sb = S + blk * gl;
 #pragma unroll
   for (int L = 0; L < kMaxOrb; ++L) {
@@ -246,14 +269,14 @@ gw_status gw_polarizability_int(const gw_cell* c, int ng, const void* Gog, const
   st = make_int_args(c, ng, q);
   if (st != GW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 gm((ng + 63) / 64, c->n_atoms, (unsigned)bl), gt((ng + kGT - 1) / kGT, (ng + kGT - 1) / kGT, (unsigned)bl);
+  const dim3 gm((ng + 255) / 256, c->n_atoms, (unsigned)bl), gt((ng + kGT - 1) / kGT, (ng + kGT - 1) / kGT, (unsigned)bl);
   if (t == GW_C128) {
-    hipLaunchKernelGGL((p_mixed<double2, 0>), gm, dim3(64), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Ppg, g, q);
-    hipLaunchKernelGGL((p_mixed<double2, 1>), gm, dim3(64), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Pgp, g, q);
+    hipLaunchKernelGGL((p_mixed<double2, 0>), gm, dim3(256), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Ppg, g, q);
+    hipLaunchKernelGGL((p_mixed<double2, 1>), gm, dim3(256), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Pgp, g, q);
     hipLaunchKernelGGL(p_gg<double2>, gt, dim3(256), 0, s, (const double2*)Ggg, (double2*)Pgg, g, q);
   } else {
-    hipLaunchKernelGGL((p_mixed<float2, 0>), gm, dim3(64), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Ppg, g, q);
-    hipLaunchKernelGGL((p_mixed<float2, 1>), gm, dim3(64), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Pgp, g, q);
+    hipLaunchKernelGGL((p_mixed<float2, 0>), gm, dim3(256), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Ppg, g, q);
+    hipLaunchKernelGGL((p_mixed<float2, 1>), gm, dim3(256), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Pgp, g, q);
     hipLaunchKernelGGL(p_gg<float2>, gt, dim3(256), 0, s, (const float2*)Ggg, (float2*)Pgg, g, q);
   }
   return check_launch("gw_polarizability_int");
@@ -281,16 +304,16 @@ gw_status gw_self_energy_int(const gw_cell* c, int ng, const void* Gog, const vo
   st = make_int_args(c, ng, q);
   if (st != GW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 gm((ng + 63) / 64, c->n_atoms, (unsigned)bl);
+  const dim3 gm((ng + 255) / 256, c->n_atoms, (unsigned)bl);
   const long long ne = (long long)ngg;
   const unsigned ge = (unsigned)((ne + 255) / 256 < 4096 ? (ne + 255) / 256 : 4096);
   if (t == GW_C128) {
-    hipLaunchKernelGGL((s_mixed<double2, 0>), gm, dim3(64), 0, s, (const double2*)Gog, (const double2*)Wpg, (double2*)Sog, q);
-    hipLaunchKernelGGL((s_mixed<double2, 1>), gm, dim3(64), 0, s, (const double2*)Ggo, (const double2*)Wgp, (double2*)Sgo, q);
+    hipLaunchKernelGGL((s_mixed<double2, 0>), gm, dim3(256), 0, s, (const double2*)Gog, (const double2*)Wpg, (double2*)Sog, q);
+    hipLaunchKernelGGL((s_mixed<double2, 1>), gm, dim3(256), 0, s, (const double2*)Ggo, (const double2*)Wgp, (double2*)Sgo, q);
     hipLaunchKernelGGL(s_gg<double2>, dim3(ge), dim3(256), 0, s, (const double2*)Ggg, (const double2*)Wgg, (double2*)Sgg, ne);
   } else {
-    hipLaunchKernelGGL((s_mixed<float2, 0>), gm, dim3(64), 0, s, (const float2*)Gog, (const float2*)Wpg, (double2*)Sog, q);
-    hipLaunchKernelGGL((s_mixed<float2, 1>), gm, dim3(64), 0, s, (const float2*)Ggo, (const float2*)Wgp, (double2*)Sgo, q);
+    hipLaunchKernelGGL((s_mixed<float2, 0>), gm, dim3(256), 0, s, (const float2*)Gog, (const float2*)Wpg, (double2*)Sog, q);
+    hipLaunchKernelGGL((s_mixed<float2, 1>), gm, dim3(256), 0, s, (const float2*)Ggo, (const float2*)Wgp, (double2*)Sgo, q);
     hipLaunchKernelGGL(s_gg<float2>, dim3(ge), dim3(256), 0, s, (const float2*)Ggg, (const float2*)Wgg, (double2*)Sgg, ne);
   }
   return check_launch("gw_self_energy_int");

@@ -67,6 +67,7 @@ constexpr int kPL = 48;       // padded pair count handled here (n <= 9)
 constexpr int kKA = kPL / 4;  // K steps over pairs
 constexpr int kMP = 64;       // padded product functions handled here (m <= 64)
 constexpr int kJT = kMP / 16;
+constexpr int kTS = 33;       // complex row stride of a wavefront's P output staging tile
 constexpr int kKJ = kMP / 4;
 
 template <class RT>
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   __shared__ CR Xs[kMaxOrb * kMaxOrb], Ys[kMaxOrb * kMaxOrb];
   __shared__ CR Qs[kPL * kQS];
   __shared__ RT Cb[kMP * kCS];
+  __shared__ __align__(16) float2 Ts[sizeof(RT) == 4 ? 4 * 16 * kTS : 1];  // FP32: [wavefront][I][J half]
   __shared__ unsigned char ta[kPL], tb[kPL], tc[kPL], td[kPL];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   if (tid < q.npA) pair_of(tid, q.nA, ta[tid], tb[tid]);
@@ -364,7 +366,60 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
         acc1 = nxt;
       }
       const int I = 16 * it + li;
-      if (I < q.mA) {
+      if constexpr (sizeof(RT) == 4) {
+        // FP32 (lane rows J = 16 Jt + 4 lk + j): the mirror block takes 128-byte runs directly,
+        // the direct block goes through a per-wavefront LDS tile and leaves as 16-byte stores
+        // along J, as in p_bf16x3
+        const float gf = (float)(-g);
+        float2* Tw = Ts + w * 16 * kTS;
+        const bool ev = ((q.Np | pB) & 1) == 0;
+#pragma unroll
+        for (int hf = 0; hf < (kJT + 1) / 2; ++hf) {
+#pragma unroll
+          for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int Jt = 2 * hf + jt, Jl = 16 * jt + M::drow(lk, j), J = 32 * hf + Jl;
+              if (Jt < kJT) {
+                const bool kp = Jt < nJT && (!LIST || (I < (k.mt & 0xffff) && J < (k.mt >> 16)));
+                Tw[li * kTS + Jl] = kp ? make_float2(gf * (float)acc2[Jt][0][j], gf * (float)acc2[Jt][1][j])
+                                       : make_float2(0.f, 0.f);
+              }
+            }
+#pragma unroll
+          for (int i4 = 0; i4 < 4; ++i4) {
+            const int rr = (lane >> 4) + 4 * i4, Jl = 2 * (lane & 15), J = 32 * hf + Jl, Ir = 16 * it + rr;
+            if (Ir < q.mA && J < q.mB) {
+              const float2 v0 = Tw[rr * kTS + Jl];
+              float2* dst = reinterpret_cast<float2*>(Pd) + (long long)(pA + Ir) * q.Np + pB + J;
+              if (J + 1 < q.mB) {
+                const float2 v1 = Tw[rr * kTS + Jl + 1];
+                if (ev) {
+                  *reinterpret_cast<float4*>(dst) = make_float4(v0.x, v0.y, v1.x, v1.y);
+                } else {
+                  dst[0] = v0;
+                  dst[1] = v1;
+                }
+              } else {
+                dst[0] = v0;
+              }
+            }
+          }
+        }
+        if (t != tm && I < q.mA) {
+#pragma unroll
+          for (int Jt = 0; Jt < kJT; ++Jt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int J = 16 * Jt + M::drow(lk, j);
+              if (Jt < nJT && J < q.mB) {
+                const bool kp = !LIST || (I < (k.mt & 0xffff) && J < (k.mt >> 16));
+                reinterpret_cast<float2*>(Pm)[(long long)(pB + J) * q.Np + pA + I] =
+                    kp ? make_float2(gf * (float)acc2[Jt][0][j], gf * (float)acc2[Jt][1][j]) : make_float2(0.f, 0.f);
+              }
+            }
+        }
+      } else if (I < q.mA) {
 #pragma unroll
         for (int Jt = 0; Jt < kJT; ++Jt)
 #pragma unroll
@@ -412,7 +467,6 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 constexpr int kQBS = 72;              // bf16 row stride of a Q^T plane
 constexpr int kQBP = kPL * kQBS;      // bf16 elements per plane
 constexpr int kCBB = 40;              // bf16 per (plane, step, J) row of C~_B
-constexpr int kTS = 33;               // complex row stride of a wavefront's output staging tile
 
 template <bool LIST = false>
 __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR, float2* __restrict__ P,

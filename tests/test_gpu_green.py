@@ -176,3 +176,4 @@ def test_count_and_mu_update_match_oracle(name):
     with pytest.raises(g.GWError):
         g.gw_update_mu(cell, dev(Hk), Gs, work, n_dev, spec.spin, target, b.mu + 5.0, b.mu + 6.0,
                        Sigma=dev(S), Sigma_x=dev(Sx))
+

@@ -521,6 +521,107 @@ def interstitial_bench(args, torch, log):
     print(json.dumps({"metric": "interstitial blocks (Eqs. 6, 7, 9, 10): HBM TB/s and FP64 TFLOP/s", "rows": rows}))
 
 
+def iteration_bench(args, torch, log):
+    """One synthetic scGW iteration of the 72-atom cell on the device, stage by stage (HIP events):
+    G(k, tau) -> G^R -> P (BF16 split) -> P(q, i nu) -> W~ (FP64 Dyson, all 48 nu x 8 q) -> W~(q, tau)
+    -> W~^R -> Sigma_c (BF16 split) -> Sigma_c(k, i w); Sigma_x; mu bisection over the G Dyson
+    solve (FP64).  Inputs: the seeded cell; V on-site (every q) = v_scale A, A Hermitian positive
+    definite (synthcell.dyson_factors); a weak v_scale keeps the synthetic self-energy small
+    enough for the tail-summed electron count."""
+    import synthcell as sc
+    import paper_1911_05633_amd as g
+    spec = sc.config(args.config)
+    C = sc.coefficients(spec)
+    cell = g.Cell.from_spec(spec, C)
+    hop = sc.hoppings(spec)
+    b = sc.bands(spec, hop)
+    nt, nk, no, npb = spec.n_tau, spec.N_R, spec.N_orb, spec.N_pb
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tau = sc.tau_grid(spec)
+    nu = g.matsubara(nt, spec.beta, "bosonic")
+    wf = g.matsubara(nt, spec.beta, "fermionic")
+    Gk = dev(sc.green_ktau(spec, b)).to(torch.complex64)
+    Hk = dev(sc.hamiltonian_k(spec, hop))
+    B = dev(sc.dyson_factors(1, npb, 1, 7)[0][0])
+    A = torch.matmul(B, B.conj().T.contiguous()) / npb
+    A.diagonal().add_(0.5)
+    V = (args.v_scale * A)[None].expand(nk, npb, npb).contiguous()
+    VR = torch.zeros((nk, npb, npb), dtype=torch.complex64, device="cuda")
+    VR[0] = V[0].to(torch.complex64)
+    del B, A
+    TP, TS = dev(g.gw_tau2omega_matrix(tau, nu)), dev(g.gw_tau2omega_matrix(tau, wf))
+    TPi = dev(g.gw_omega2tau_matrix(tau, nu))
+    GR = torch.empty_like(Gk)
+    P = torch.empty((nt, nk, npb, npb), dtype=torch.complex64, device="cuda")
+    S = torch.empty((nt, nk, no, no), dtype=torch.complex128, device="cuda")
+    SxR = torch.empty((nk, no, no), dtype=torch.complex128, device="cuda")
+    Gw = torch.empty_like(S)
+    chunk = min(nt * nk, 64)
+    work_w = torch.empty(g.gw_screened_interaction_workspace(cell, chunk), dtype=torch.uint8, device="cuda")
+    work_g = torch.empty(g.gw_green_dyson_workspace(cell, nt * nk), dtype=torch.uint8, device="cuda")
+    n_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    stages = []
+    mu_box = {}
+    Sx_stack = torch.empty((nt, nk, no, no), dtype=torch.complex128, device="cuda")
+
+    def sx_k():
+        # Sigma_x(k) = sum_R exp(-i k.R) Sigma_x^R through the library's R -> k sum (slice 0 kept)
+        Sx_stack[0].copy_(SxR)
+        g.gw_fourier_r2k(cell, Sx_stack, Sx_stack, basis=0)
+
+    def count_at(mu):
+        g.gw_green_dyson(cell, Hk, mu, Gw, work_g, Sigma=S, Sigma_x=Sx_stack[0], info=info)
+        g.gw_density_omega(cell, Gw, Hk, mu, spec.spin, n_dev, Sigma_x=Sx_stack[0])
+        torch.cuda.synchronize()
+        return float(n_dev.item()), int(info.item())
+
+    def mu_update():
+        target = spec.spin * no / 2.0
+        lo, hi = b.mu - 1.0, b.mu + 1.0
+        for _ in range(6):   # widen the bracket until it holds the target count
+            (n_lo, i_lo), (n_hi, i_hi) = count_at(lo), count_at(hi)
+            log(f"mu bracket [{lo:.3f}, {hi:.3f}]: counts {n_lo:.4f} .. {n_hi:.4f} (target {target}), "
+                f"pivot reports {i_lo}, {i_hi}")
+            if n_lo <= target <= n_hi:
+                break
+            lo, hi = lo - 2.0 * (hi - lo), hi + 2.0 * (hi - lo)
+        mu_box["mu"], mu_box["n"] = g.gw_update_mu(cell, Hk, Gw, work_g, n_dev, spec.spin, target, lo, hi,
+                                                  tol=1e-8, max_iter=60, Sigma=S, Sigma_x=Sx_stack[0])
+
+    plan = [
+        ("k2r G", lambda: g.gw_fourier_k2r(cell, Gk, GR, basis=0)),
+        ("P", lambda: g.gw_polarizability(cell, GR, P, spec.spin, prec="bf16x3")),
+        ("drain P", lambda: g.gw_drain(cell, TP, P, P, basis=1, parity=1)),
+        ("W Dyson", lambda: g.gw_screened_interaction(cell, V, P, P, work_w, info=info)),
+        ("W nu->tau", lambda: g.gw_tau2omega(cell, TPi, P, P, basis=1, parity=0)),
+        ("W q->R", lambda: g.gw_fourier_k2r(cell, P, P, basis=1)),
+        ("Sigma", lambda: g.gw_self_energy(cell, GR, P, S, prec="bf16x3")),
+        ("drain Sigma", lambda: g.gw_drain(cell, TS, S, S, basis=0, parity=-1)),
+        ("Sigma_x", lambda: g.gw_exchange(cell, GR, VR, SxR, prec="bf16x3")),
+        ("Sigma_x R->k", sx_k),
+        ("mu + G Dyson", mu_update),
+    ]
+    log(f"iteration {spec.name}: max |Sigma_c(k, i w)| follows the W stage")
+    t0 = time.perf_counter()
+    for name, fn in plan:
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        e.record()
+        torch.cuda.synchronize()
+        stages.append({"stage": name, "ms": a.elapsed_time(e)})
+        log(f"iteration {spec.name}: {name} {stages[-1]['ms']:.2f} ms")
+        if name == "drain Sigma":
+            log(f"iteration {spec.name}: max |Sigma_c(k, i w)| = {S.abs().max().item():.4g}, W pivot report "
+                f"{int(info.item())}")
+    wall = time.perf_counter() - t0
+    print(json.dumps({"metric": "one synthetic scGW iteration, stage times (ms)", "cell": spec.name,
+                      "total_s": wall, "stages": stages, "W_info": int(info.item()), "mu": mu_box.get("mu"),
+                      "count": mu_box.get("n")}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -542,6 +643,9 @@ def main():
                     help="time the screened interaction (Eq. 2) on the 8- and 72-atom cells and exit")
     ap.add_argument("--interstitial", action="store_true",
                     help="time the interstitial-grid blocks of P and Sigma and exit")
+    ap.add_argument("--iteration", action="store_true",
+                    help="time one synthetic scGW iteration (P, W, Sigma, Sigma_x, mu and G) stage by stage and exit")
+    ap.add_argument("--v-scale", type=float, default=1e-4, help="bare interaction scale of --iteration")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -571,6 +675,9 @@ def main():
         return
     if args.interstitial:
         interstitial_bench(args, torch, log)
+        return
+    if args.iteration:
+        iteration_bench(args, torch, log)
         return
     spec = sc.config(args.config)
     log(f"config {args.config}: {spec.name}, {spec.n_atoms} atoms, N_orb {spec.N_orb}, N_pb {spec.N_pb}, "

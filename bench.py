@@ -381,27 +381,38 @@ def dyson_bench(args, torch, log):
             torch.mul(XX, -float(s[m]), out=P[m])
         W = torch.empty_like(P)
         total = n_nu * nk
-        work = torch.empty(g.gw_screened_interaction_workspace(cell, total), dtype=torch.uint8, device="cuda")
         info = torch.zeros(1, dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
         log(f"dyson {spec.name}: inputs in {time.time() - t0:.1f}s; {total} (q, nu) matrices of {n}")
-        g.gw_screened_interaction(cell, V, P, W, work, info=info)
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        for a, b in ev:
-            a.record()
-            g.gw_screened_interaction(cell, V, P, W, work, info=info)
-            b.record()
-        torch.cuda.synchronize()
-        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-        flops = 8.0 * n ** 3 * (total + nk)
-        # sampled parity against the oracle
         Vh = V.cpu().numpy()
-        err = 0.0
-        for m, q in ((0, 0), (n_nu - 1, nk - 1)):
-            ref = oracle.screened_interaction(Vh[q:q + 1], P[m:m + 1, q:q + 1].cpu().numpy())[0, 0]
-            got = W[m, q].cpu().numpy()
-            err = max(err, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+        for prec in ("fp64", "fp32"):
+            work = torch.empty(g.gw_screened_interaction_workspace(cell, total, prec), dtype=torch.uint8,
+                               device="cuda")
+            g.gw_screened_interaction(cell, V, P, W, work, info=info, prec=prec)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            for a, b in ev:
+                a.record()
+                g.gw_screened_interaction(cell, V, P, W, work, info=info, prec=prec)
+                b.record()
+            torch.cuda.synchronize()
+            ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            flops = 8.0 * n ** 3 * (total + nk)
+            # sampled parity against the oracle
+            err = 0.0
+            for m, q in ((0, 0), (n_nu - 1, nk - 1)):
+                ref = oracle.screened_interaction(Vh[q:q + 1], P[m:m + 1, q:q + 1].cpu().numpy())[0, 0]
+                got = W[m, q].cpu().numpy()
+                err = max(err, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+            peak = PEAK["fp64"] if prec == "fp64" else PEAK["fp32"]
+            rows.append({"cell": spec.name, "prec": prec, "N_pb": n, "N_k": nk, "n_nu": n_nu, "matrices": total,
+                         "ms": ms, "ms_per_matrix": ms / total, "gflops": flops / (ms * 1e-3) / 1e9,
+                         "frac_peak": flops / (ms * 1e-3) / peak, "info": int(info.item()),
+                         "max_rel_err_sampled": err})
+            log(f"dyson {spec.name} {prec}: {ms:.2f} ms, {rows[-1]['gflops']:.0f} GFLOP/s, info {rows[-1]['info']}, "
+                f"sampled rel err {err:.2e}")
+            del work
+            torch.cuda.empty_cache()
         if cfg == 2 and not args.no_cpu:
             Ph = P[0:1, 0:2].cpu().numpy()
             c0 = time.perf_counter()
@@ -409,13 +420,7 @@ def dyson_bench(args, torch, log):
             secs = time.perf_counter() - c0
             cpu = {"value": 8.0 * n ** 3 * 2 / secs / 1e9, "unit": "GFLOP/s", "cores": os.cpu_count(),
                    "kind": "oracle", "sample": f"numpy LU solve of 2 (q, nu) systems of {n}: {secs:.2f} s"}
-        rows.append({"cell": spec.name, "N_pb": n, "N_k": nk, "n_nu": n_nu, "matrices": total,
-                     "ms": ms, "ms_per_matrix": ms / total, "gflops": flops / (ms * 1e-3) / 1e9,
-                     "frac_fp64_peak": flops / (ms * 1e-3) / PEAK["fp64"], "info": int(info.item()),
-                     "max_rel_err_sampled": err})
-        log(f"dyson {spec.name}: {ms:.2f} ms, {rows[-1]['gflops']:.0f} GFLOP/s, info {rows[-1]['info']}, "
-            f"sampled rel err {err:.2e}")
-        del V, XX, P, W, work
+        del V, XX, P, W
         torch.cuda.empty_cache()
     green, exch = [], []
     for cfg in (2, 3):
@@ -557,7 +562,8 @@ def iteration_bench(args, torch, log):
     SxR = torch.empty((nk, no, no), dtype=torch.complex128, device="cuda")
     Gw = torch.empty_like(S)
     chunk = min(nt * nk, 64)
-    work_w = torch.empty(g.gw_screened_interaction_workspace(cell, chunk), dtype=torch.uint8, device="cuda")
+    work_w = torch.empty(g.gw_screened_interaction_workspace(cell, chunk, args.w_prec), dtype=torch.uint8,
+                         device="cuda")
     work_g = torch.empty(g.gw_green_dyson_workspace(cell, nt * nk), dtype=torch.uint8, device="cuda")
     n_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -594,7 +600,7 @@ def iteration_bench(args, torch, log):
         ("k2r G", lambda: g.gw_fourier_k2r(cell, Gk, GR, basis=0)),
         ("P", lambda: g.gw_polarizability(cell, GR, P, spec.spin, prec="bf16x3")),
         ("drain P", lambda: g.gw_drain(cell, TP, P, P, basis=1, parity=1)),
-        ("W Dyson", lambda: g.gw_screened_interaction(cell, V, P, P, work_w, info=info)),
+        ("W Dyson", lambda: g.gw_screened_interaction(cell, V, P, P, work_w, info=info, prec=args.w_prec)),
         ("W nu->tau", lambda: g.gw_tau2omega(cell, TPi, P, P, basis=1, parity=0)),
         ("W q->R", lambda: g.gw_fourier_k2r(cell, P, P, basis=1)),
         ("Sigma", lambda: g.gw_self_energy(cell, GR, P, S, prec="bf16x3")),
@@ -618,6 +624,7 @@ def iteration_bench(args, torch, log):
                 f"{int(info.item())}")
     wall = time.perf_counter() - t0
     print(json.dumps({"metric": "one synthetic scGW iteration, stage times (ms)", "cell": spec.name,
+                      "w_prec": args.w_prec,
                       "total_s": wall, "stages": stages, "W_info": int(info.item()), "mu": mu_box.get("mu"),
                       "count": mu_box.get("n")}))
 
@@ -646,6 +653,8 @@ def main():
     ap.add_argument("--iteration", action="store_true",
                     help="time one synthetic scGW iteration (P, W, Sigma, Sigma_x, mu and G) stage by stage and exit")
     ap.add_argument("--v-scale", type=float, default=1e-4, help="bare interaction scale of --iteration")
+    ap.add_argument("--w-prec", default="fp64", choices=["fp64", "fp32"],
+                    help="elimination precision of the W step in --iteration")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()

@@ -235,21 +235,24 @@ gw_status gw_exchange(const gw_cell* cell, const void* GR, const void* VR, void*
  *       Matsubara frequencies), so that V^-1 - P has a positive definite Hermitian part: then
  *       every leading block is invertible and every pivot has a positive real part;
  *   W:  DEVICE, P's shape, w_type storage; may be P itself when p_type == w_type, else disjoint;
- *   work, work_size: DEVICE scratch of at least gw_screened_interaction_workspace(cell, 1)
+ *   prec: GW_FP64 runs both eliminations in FP64; GW_FP32 (and GW_BF16X3) in FP32 on complex64
+ *       working copies (relative error about cond * 1e-7; the final W - V subtraction in FP64);
+ *   work, work_size: DEVICE scratch of at least gw_screened_interaction_workspace(cell, 1, prec)
  *       bytes, owned by the caller and not retained; more lets more (q, nu) matrices be
  *       inverted per launch (up to the size for chunk = n_omega * N_k);
  *   info: NULL, or a DEVICE int set to 0, then to -(q + 1) if V(q) or to 1 + nu * N_k + q if
  *       V(q)^-1 - P(q, nu) met a pivot whose real part is not positive (one such matrix is
  *       named; the outputs are then not to be trusted).  Read it after the stream completes.
- * Both inverses are blocked Gauss-Jordan eliminations without pivoting, in FP64, on the
- * matrices padded to a multiple of 64 with the identity.  Enqueued on `stream`. */
+ * Both inverses are blocked Gauss-Jordan eliminations without pivoting, on the matrices
+ * padded to a multiple of 64 with the identity.  Enqueued on `stream`. */
 gw_status gw_screened_interaction(const gw_cell* cell, const void* V, const void* P, gw_dtype p_type, void* W,
-                                  gw_dtype w_type, int n_omega, void* work, size_t work_size, int* info,
-                                  void* stream);
+                                  gw_dtype w_type, int n_omega, gw_precision prec, void* work, size_t work_size,
+                                  int* info, void* stream);
 
-/* Workspace bytes gw_screened_interaction needs to invert `chunk` (q, nu) matrices per launch:
- * 16 * (Np^2 * (N_k + chunk) + 4096 * max(N_k, chunk)), Np = N_pb rounded up to 64. */
-gw_status gw_screened_interaction_workspace(const gw_cell* cell, int chunk, size_t* bytes);
+/* Workspace bytes gw_screened_interaction needs to invert `chunk` (q, nu) matrices per launch
+ * at precision prec: e * (Np^2 * (N_k + chunk) + 4096 * max(N_k, chunk)), Np = N_pb rounded up
+ * to 64, e = 16 for GW_FP64 and 8 otherwise. */
+gw_status gw_screened_interaction_workspace(const gw_cell* cell, int chunk, gw_precision prec, size_t* bytes);
 
 /* Dyson equation for the Green's function, Eq. (4), with the Hartree-level G0^-1 = (i w + mu) - H:
  *   G(k, i w_m) = [(i w_m + mu) I - H(k) - Sigma_x(k) - Sigma(k, i w_m)]^-1,

@@ -46,8 +46,9 @@ SIGNATURES = {
     "gw_polarizability_int": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _c_double, _c_int, _vp]),
     "gw_self_energy_int": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_exchange": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
-    "gw_screened_interaction": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_int, _c_int, _vp, ctypes.c_size_t, _vp, _vp]),
-    "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "gw_screened_interaction": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_int, _c_int, _c_int, _vp, ctypes.c_size_t,
+                                         _vp, _vp]),
+    "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "gw_green_dyson": (_c_int, [_vp, _vp, _c_double, _c_int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "gw_green_dyson_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "gw_density_omega": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _c_double, _c_double, _vp, _vp]),
@@ -338,15 +339,16 @@ def gw_exchange(cell, GR, VR, Sigma_x, prec=None):
                            _ptr(Sigma_x, cell.elems(0, 1), "Sigma_x"), p, _stream()), "gw_exchange")
 
 
-def gw_screened_interaction_workspace(cell, chunk=1):
-    """Workspace bytes for `chunk` (q, nu) matrices per launch."""
+def gw_screened_interaction_workspace(cell, chunk=1, prec="fp64"):
+    """Workspace bytes for `chunk` (q, nu) matrices per launch at precision prec."""
     b = ctypes.c_size_t()
-    _check(lib.gw_screened_interaction_workspace(cell.handle, int(chunk), ctypes.byref(b)),
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    _check(lib.gw_screened_interaction_workspace(cell.handle, int(chunk), p, ctypes.byref(b)),
            "gw_screened_interaction_workspace")
     return b.value
 
 
-def gw_screened_interaction(cell, V, P, W, work, info=None):
+def gw_screened_interaction(cell, V, P, W, work, info=None, prec="fp64"):
     """W~(q, nu) = (I - V(q) P(q, nu))^-1 V(q) - V(q) for P of shape [n_omega][N_k][N_pb][N_pb].
 
     V: complex128 device [N_k][N_pb][N_pb]; work: a device tensor (any dtype) used as scratch;
@@ -366,8 +368,9 @@ def gw_screened_interaction(cell, V, P, W, work, info=None):
         if info.dtype != torch.int32 or info.numel() != 1:
             raise ValueError("info must be a one-element int32 device tensor")
         ip = _ptr(info, 1, "info")
+    p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
     _check(lib.gw_screened_interaction(cell.handle, _ptr(V, per, "V"), _ptr(P, P.numel(), "P"), _dtype_code(P),
-                                       _ptr(W, P.numel(), "W"), _dtype_code(W), n_omega,
+                                       _ptr(W, P.numel(), "W"), _dtype_code(W), n_omega, p,
                                        ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size(), ip,
                                        _stream()), "gw_screened_interaction")
 

@@ -40,35 +40,35 @@ __global__ void dy_zero_info(int* info) {
 }
 
 // mode 0: M[c] = V[q0 + c];  mode 1: M[c] = Vinv[q] - P[g] with g = g0 + c, q = g mod N_k.
-// Indices beyond n hold the identity.
-template <class PT>
-__global__ __launch_bounds__(256) void dy_load(double2* __restrict__ M, long long per, int np, int n, int mode,
-                                               const double2* __restrict__ Vsrc, const PT* __restrict__ P,
-                                               long long g0, int n_k) {
+// Indices beyond n hold the identity.  MT: complex type the elimination runs in.
+template <class PT, class MT>
+__global__ __launch_bounds__(256) void dy_load(MT* __restrict__ M, long long per, int np, int n, int mode,
+                                               const double2* __restrict__ V, const MT* __restrict__ Vinv,
+                                               const PT* __restrict__ P, long long g0, int n_k) {
   const int c = blockIdx.y;
   const long long g = g0 + c;
   const int q = mode == 0 ? (int)g : (int)(g % n_k);
-  double2* Mc = M + (long long)c * per;
+  MT* Mc = M + (long long)c * per;
   const long long nn = (long long)np * np;
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long long)gridDim.x * 256) {
     const int i = (int)(e / np), j = (int)(e - (long long)i * np);
     double2 v = make_double2(i == j ? 1.0 : 0.0, 0.0);
     if (i < n && j < n) {
       if (mode == 0) {
-        v = Vsrc[((long long)q * n + i) * n + j];
+        v = V[((long long)q * n + i) * n + j];
       } else {
-        const double2 a = Vsrc[(long long)q * per + e];
+        const double2 a = ld2(Vinv + (long long)q * per + e);
         const double2 p = ld2(P + (g * n + i) * n + j);
         v = make_double2(a.x - p.x, a.y - p.y);
       }
     }
-    Mc[e] = v;
+    st2(Mc + e, v);
   }
 }
 
-// W[g] = M[c] - V[q] on the n x n corner
-template <class WT>
-__global__ __launch_bounds__(256) void dy_store(const double2* __restrict__ M, long long per, int np, int n,
+// W[g] = M[c] - V[q] on the n x n corner (the subtraction in FP64)
+template <class WT, class MT>
+__global__ __launch_bounds__(256) void dy_store(const MT* __restrict__ M, long long per, int np, int n,
                                                 const double2* __restrict__ V, WT* __restrict__ W, long long g0,
                                                 int n_k) {
   const int c = blockIdx.y;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void dy_store(const double2* __restrict__ M, l
   const long long nn = (long long)n * n;
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long long)gridDim.x * 256) {
     const int i = (int)(e / n), j = (int)(e - (long long)i * n);
-    const double2 a = M[(long long)c * per + (long long)i * np + j];
+    const double2 a = ld2(M + (long long)c * per + (long long)i * np + j);
     const double2 v = V[(long long)q * nn + e];
     st2(W + g * nn + e, make_double2(a.x - v.x, a.y - v.y));
   }
@@ -164,18 +164,26 @@ __global__ __launch_bounds__(256) void dy_count(const double2* __restrict__ G, c
   if (threadIdx.x == 0) *n_dev = g / n_k * (0.5 * (double)n_k * n + 2.0 / beta * part[0]);
 }
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
+template <class MT> struct Cx;
+template <> struct Cx<double2> {
+  typedef double R;
+  static __device__ __forceinline__ double2 mk(double x, double y) { return make_double2(x, y); }
+};
+template <> struct Cx<float2> {
+  typedef float R;
+  static __device__ __forceinline__ float2 mk(float x, float y) { return make_float2(x, y); }
+};
 
 // Inverse of the diagonal block of step k by in-place Gauss-Jordan; written to Dinv[c] and to
 // M[c][K,K].  A pivot whose real part is not positive flags the matrix in *info.
-__global__ __launch_bounds__(256) void dy_diag(double2* __restrict__ M, double2* __restrict__ Dinv, long long per,
-                                               int np, int k, int* info, int code0, int sign) {
-  __shared__ double2 D[kDB * kDS];
-  __shared__ double2 Rw[kDB], Fc[kDB];
+template <class MT>
+__global__ __launch_bounds__(256) void dy_diag(MT* __restrict__ M, MT* __restrict__ Dinv, long long per, int np,
+                                               int k, int* info, int code0, int sign) {
+  typedef typename Cx<MT>::R R;
+  __shared__ MT D[kDB * kDS];
+  __shared__ MT Rw[kDB], Fc[kDB];
   const int c = blockIdx.x, tid = threadIdx.x;
-  double2* Mk = M + (long long)c * per + (long long)k * kDB * np + (long long)k * kDB;
+  MT* Mk = M + (long long)c * per + (long long)k * kDB * np + (long long)k * kDB;
   for (int e = tid; e < kDB * kDB; e += 256) {
     const int i = e >> 6, j = e & 63;
     D[i * kDS + j] = Mk[(long long)i * np + j];
@@ -183,16 +191,17 @@ __global__ __launch_bounds__(256) void dy_diag(double2* __restrict__ M, double2*
   __syncthreads();
   const int i = tid >> 2, j0 = tid & 3;
   for (int p = 0; p < kDB; ++p) {
-    const double2 piv = D[p * kDS + p];
-    const double den = piv.x * piv.x + piv.y * piv.y;
-    const double2 inv = make_double2(piv.x / den, -piv.y / den);
-    if (tid == 0 && info && !(piv.x > 0.0 && std::isfinite(piv.x) && std::isfinite(piv.y)))
+    const MT piv = D[p * kDS + p];
+    const R den = piv.x * piv.x + piv.y * piv.y;
+    const MT inv = Cx<MT>::mk(piv.x / den, -piv.y / den);
+    if (tid == 0 && info && !(piv.x > R(0) && std::isfinite(piv.x) && std::isfinite(piv.y)))
       atomicCAS(info, 0, sign * (code0 + c + 1));
     if (tid < kDB) {
-      Rw[tid] = tid == p ? inv : cmul(D[p * kDS + tid], inv);
+      const MT a = D[p * kDS + tid];
+      Rw[tid] = tid == p ? inv : Cx<MT>::mk(a.x * inv.x - a.y * inv.y, a.x * inv.y + a.y * inv.x);
     } else if (tid < 2 * kDB) {
       const int r = tid - kDB;
-      Fc[r] = r == p ? make_double2(0.0, 0.0) : D[r * kDS + p];
+      Fc[r] = r == p ? Cx<MT>::mk(R(0), R(0)) : D[r * kDS + p];
     }
     __syncthreads();
 #pragma unroll 4
@@ -201,17 +210,17 @@ __global__ __launch_bounds__(256) void dy_diag(double2* __restrict__ M, double2*
       if (i == p) {
         D[p * kDS + j] = Rw[j];
       } else {
-        const double2 b = j == p ? make_double2(0.0, 0.0) : D[i * kDS + j];
-        const double2 f = Fc[i], r = Rw[j];
-        D[i * kDS + j] = make_double2(b.x - (f.x * r.x - f.y * r.y), b.y - (f.x * r.y + f.y * r.x));
+        const MT b = j == p ? Cx<MT>::mk(R(0), R(0)) : D[i * kDS + j];
+        const MT f = Fc[i], r = Rw[j];
+        D[i * kDS + j] = Cx<MT>::mk(b.x - (f.x * r.x - f.y * r.y), b.y - (f.x * r.y + f.y * r.x));
       }
     }
     __syncthreads();
   }
-  double2* Dc = Dinv + (long long)c * kDB * kDB;
+  MT* Dc = Dinv + (long long)c * kDB * kDB;
   for (int e = tid; e < kDB * kDB; e += 256) {
     const int r = e >> 6, s = e & 63;
-    const double2 v = D[r * kDS + s];
+    const MT v = D[r * kDS + s];
     Dc[e] = v;
     Mk[(long long)r * np + s] = v;
   }
@@ -224,18 +233,19 @@ __global__ __launch_bounds__(256) void dy_diag(double2* __restrict__ M, double2*
 // Thread (ty, tx) = (tid / 16, tid % 16) owns rows ty + 16 a and columns tx + 16 b of the tile.
 // A tile that is both read and written belongs to one workgroup, which reads all of it before
 // the last barrier and writes after it.
-template <int OP>
-__global__ __launch_bounds__(256) void dy_tile(double2* __restrict__ M, const double2* __restrict__ Dinv,
+template <int OP, class MT>
+__global__ __launch_bounds__(256) void dy_tile(MT* __restrict__ M, const MT* __restrict__ Dinv,
                                                long long per, int np, int k) {
-  __shared__ double2 As[kDB * (kKC + 1)];
-  __shared__ double2 Bs[kKC * kDB];
+  typedef typename Cx<MT>::R R;
+  __shared__ MT As[kDB * (kKC + 1)];
+  __shared__ MT Bs[kKC * kDB];
   const int c = blockIdx.z, tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  double2* Mc = M + (long long)c * per;
-  const double2* Dc = Dinv + (long long)c * kDB * kDB;
+  MT* Mc = M + (long long)c * per;
+  const MT* Dc = Dinv + (long long)c * kDB * kDB;
   const long long K0 = (long long)k * kDB;
-  const double2 *A, *B;
+  const MT *A, *B;
   long long lda, ldb;
-  double2* C;
+  MT* C;
   if (OP == 0) {
     const int J = blockIdx.x;
     if (J == k) return;
@@ -261,11 +271,11 @@ __global__ __launch_bounds__(256) void dy_tile(double2* __restrict__ M, const do
     ldb = kDB;
     C = Mc + (long long)I * kDB * np + K0;
   }
-  double2 acc[4][4];
+  MT acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int b = 0; b < 4; ++b) acc[a][b] = Cx<MT>::mk(R(0), R(0));
   for (int k0 = 0; k0 < kDB; k0 += kKC) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -278,7 +288,7 @@ __global__ __launch_bounds__(256) void dy_tile(double2* __restrict__ M, const do
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < kKC; ++kk) {
-      double2 av[4], bv[4];
+      MT av[4], bv[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = As[(ty + 16 * a) * (kKC + 1) + kk];
 #pragma unroll
@@ -297,14 +307,14 @@ __global__ __launch_bounds__(256) void dy_tile(double2* __restrict__ M, const do
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      double2* d = C + (long long)(ty + 16 * a) * np + tx + 16 * b;
+      MT* d = C + (long long)(ty + 16 * a) * np + tx + 16 * b;
       if (OP == 0) {
         *d = acc[a][b];
       } else if (OP == 1) {
-        const double2 v = *d;
-        *d = make_double2(v.x - acc[a][b].x, v.y - acc[a][b].y);
+        const MT v = *d;
+        *d = Cx<MT>::mk(v.x - acc[a][b].x, v.y - acc[a][b].y);
       } else {
-        *d = make_double2(-acc[a][b].x, -acc[a][b].y);
+        *d = Cx<MT>::mk(-acc[a][b].x, -acc[a][b].y);
       }
     }
 }
@@ -315,15 +325,16 @@ unsigned grid_elems(long long n) {
 }
 
 // in-place inverse of `count` padded matrices M[c] (stride per); info codes sign * (code0 + c + 1)
-gw_status gj_invert(double2* M, double2* Dinv, int count, int np, int* info, int code0, int sign, hipStream_t s) {
+template <class MT>
+gw_status gj_invert(MT* M, MT* Dinv, int count, int np, int* info, int code0, int sign, hipStream_t s) {
   const long long per = (long long)np * np;
   const int nt = np / kDB;
   for (int k = 0; k < nt; ++k) {
-    hipLaunchKernelGGL(dy_diag, dim3(count), dim3(256), 0, s, M, Dinv, per, np, k, info, code0, sign);
+    hipLaunchKernelGGL(dy_diag<MT>, dim3(count), dim3(256), 0, s, M, Dinv, per, np, k, info, code0, sign);
     if (nt > 1) {
-      hipLaunchKernelGGL(dy_tile<0>, dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
-      hipLaunchKernelGGL(dy_tile<1>, dim3(nt, nt, count), dim3(256), 0, s, M, Dinv, per, np, k);
-      hipLaunchKernelGGL(dy_tile<2>, dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL((dy_tile<0, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL((dy_tile<1, MT>), dim3(nt, nt, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL((dy_tile<2, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
     }
   }
   return check_launch("screened interaction: elimination");
@@ -331,9 +342,10 @@ gw_status gj_invert(double2* M, double2* Dinv, int count, int np, int* info, int
 
 int padded(int n) { return (n + kDB - 1) / kDB * kDB; }
 
-size_t work_bytes(int n_k, int np, long long chunk) {
+// es: bytes per complex element of the elimination (16 for FP64, 8 for FP32)
+size_t work_bytes(int n_k, int np, long long chunk, size_t es) {
   const long long nd = chunk > n_k ? chunk : n_k;
-  return 16 * ((size_t)np * np * (size_t)(n_k + chunk) + (size_t)kDB * kDB * (size_t)nd);
+  return es * ((size_t)np * np * (size_t)(n_k + chunk) + (size_t)kDB * kDB * (size_t)nd);
 }
 
 size_t green_bytes(int np, long long chunk) {
@@ -352,37 +364,86 @@ using namespace gwr;
 
 extern "C" {
 
-gw_status gw_screened_interaction_workspace(const gw_cell* c, int chunk, size_t* bytes) {
+gw_status gw_screened_interaction_workspace(const gw_cell* c, int chunk, gw_precision prec, size_t* bytes) {
   if (!c || !bytes) return fail(GW_ERR_ARG, "NULL pointer");
   if (chunk < 1) return fail(GW_ERR_ARG, "chunk must be >= 1");
-  *bytes = work_bytes(c->N_R, padded(c->N_pb), chunk);
+  if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return fail(GW_ERR_ARG, "bad precision");
+  *bytes = work_bytes(c->N_R, padded(c->N_pb), chunk, prec == GW_FP64 ? 16 : 8);
   return GW_OK;
 }
 
+}  // extern "C"
+
+namespace gwr {
+namespace {
+
+// the elimination of gw_screened_interaction in the complex type MT (double2 or float2)
+template <class MT>
+gw_status screened_run(const gw_cell* c, const void* V, const void* P, gw_dtype pt, void* W, gw_dtype wt,
+                       long long total, long long chunk, void* work, int* info, hipStream_t s) {
+  const int n_k = c->N_R, n = c->N_pb, np = padded(n);
+  const long long per = (long long)np * np;
+  MT* Vinv = static_cast<MT*>(work);
+  MT* Mw = Vinv + (long long)n_k * per;
+  MT* Dinv = Mw + chunk * per;
+  if (info) hipLaunchKernelGGL(dy_zero_info, dim3(1), dim3(64), 0, s, info);
+  // V^-1 for every q (flag -(q + 1) on a non-positive pivot)
+  hipLaunchKernelGGL((dy_load<double2, MT>), dim3(grid_elems(per), n_k), dim3(256), 0, s, Vinv, per, np, n, 0,
+                     (const double2*)V, (const MT*)nullptr, (const double2*)nullptr, 0LL, n_k);
+  gw_status st = gj_invert(Vinv, Dinv, n_k, np, info, 0, -1, s);
+  if (st != GW_OK) return st;
+  for (long long g0 = 0; g0 < total; g0 += chunk) {
+    const int cnt = (int)(total - g0 < chunk ? total - g0 : chunk);
+    if (pt == GW_C128)
+      hipLaunchKernelGGL((dy_load<double2, MT>), dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n, 1,
+                         (const double2*)nullptr, (const MT*)Vinv, (const double2*)P, g0, n_k);
+    else
+      hipLaunchKernelGGL((dy_load<float2, MT>), dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n, 1,
+                         (const double2*)nullptr, (const MT*)Vinv, (const float2*)P, g0, n_k);
+    st = gj_invert(Mw, Dinv, cnt, np, info, (int)g0, 1, s);
+    if (st != GW_OK) return st;
+    if (wt == GW_C128)
+      hipLaunchKernelGGL((dy_store<double2, MT>), dim3(grid_elems((long long)n * n), cnt), dim3(256), 0, s,
+                         (const MT*)Mw, per, np, n, (const double2*)V, (double2*)W, g0, n_k);
+    else
+      hipLaunchKernelGGL((dy_store<float2, MT>), dim3(grid_elems((long long)n * n), cnt), dim3(256), 0, s,
+                         (const MT*)Mw, per, np, n, (const double2*)V, (float2*)W, g0, n_k);
+  }
+  return check_launch("gw_screened_interaction");
+}
+
+}  // namespace
+}  // namespace gwr
+
+extern "C" {
+
 gw_status gw_screened_interaction(const gw_cell* c, const void* V, const void* P, gw_dtype pt, void* W, gw_dtype wt,
-                                  int n_omega, void* work, size_t work_size, int* info, void* stream) {
+                                  int n_omega, gw_precision prec, void* work, size_t work_size, int* info,
+                                  void* stream) {
   if (!c) return fail(GW_ERR_ARG, "cell is NULL");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return fail(GW_ERR_HIP, "hipGetDevice failed");
   if (cur != c->device) return fail(GW_ERR_ARG, "current device differs from the cell's device");
   if (!V || !P || !W || !work) return fail(GW_ERR_ARG, "NULL pointer");
   if ((pt != GW_C128 && pt != GW_C64) || (wt != GW_C128 && wt != GW_C64)) return fail(GW_ERR_ARG, "bad dtype");
+  if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return fail(GW_ERR_ARG, "bad precision");
   if (n_omega < 1) return fail(GW_ERR_SHAPE, "n_omega must be >= 1");
+  const size_t es = prec == GW_FP64 ? 16 : 8;
   const int n_k = c->N_R, n = c->N_pb, np = padded(n);
   const long long total = (long long)n_omega * n_k;
   long long chunk = 0;
-  if (work_size >= work_bytes(n_k, np, 1)) {
+  if (work_size >= work_bytes(n_k, np, 1, es)) {
     long long lo = 1, hi = total;
     while (lo < hi) {
       const long long mid = (lo + hi + 1) / 2;
-      if (work_bytes(n_k, np, mid) <= work_size) lo = mid; else hi = mid - 1;
+      if (work_bytes(n_k, np, mid, es) <= work_size) lo = mid; else hi = mid - 1;
     }
     chunk = lo;
   }
-  if (chunk < 1) return fail(GW_ERR_SHAPE, "workspace smaller than gw_screened_interaction_workspace(cell, 1)");
+  if (chunk < 1) return fail(GW_ERR_SHAPE, "workspace smaller than gw_screened_interaction_workspace(cell, 1, prec)");
   if (chunk > 65535) chunk = 65535;
   const size_t nv = (size_t)n_k * n * n * 16, npw = (size_t)total * n * n;
-  const size_t bp = npw * csize(pt), bw = npw * csize(wt), bwork = work_bytes(n_k, np, chunk);
+  const size_t bp = npw * csize(pt), bw = npw * csize(wt), bwork = work_bytes(n_k, np, chunk, es);
   if (!disjoint(V, nv, W, bw) || !disjoint(work, bwork, V, nv) || !disjoint(work, bwork, P, bp) ||
       !disjoint(work, bwork, W, bw))
     return fail(GW_ERR_ARG, "the workspace or V overlaps another operand");
@@ -390,35 +451,9 @@ gw_status gw_screened_interaction(const gw_cell* c, const void* V, const void* P
     return fail(GW_ERR_ARG, "P and W must be the same tensor of one dtype, or disjoint");
   if (info && (!disjoint(info, 4, work, bwork) || !disjoint(info, 4, W, bw)))
     return fail(GW_ERR_ARG, "info overlaps an operand");
-  hipStream_t s = (hipStream_t)stream;
-  const long long per = (long long)np * np;
-  double2* Vinv = static_cast<double2*>(work);
-  double2* Mw = Vinv + (long long)n_k * per;
-  double2* Dinv = Mw + chunk * per;
-  if (info) hipLaunchKernelGGL(dy_zero_info, dim3(1), dim3(64), 0, s, info);
-  // V^-1 for every q (flag -(q + 1) on a non-positive pivot)
-  hipLaunchKernelGGL(dy_load<double2>, dim3(grid_elems(per), n_k), dim3(256), 0, s, Vinv, per, np, n, 0,
-                     (const double2*)V, (const double2*)nullptr, 0LL, n_k);
-  gw_status st = gj_invert(Vinv, Dinv, n_k, np, info, 0, -1, s);
-  if (st != GW_OK) return st;
-  for (long long g0 = 0; g0 < total; g0 += chunk) {
-    const int cnt = (int)(total - g0 < chunk ? total - g0 : chunk);
-    if (pt == GW_C128)
-      hipLaunchKernelGGL(dy_load<double2>, dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n, 1,
-                         (const double2*)Vinv, (const double2*)P, g0, n_k);
-    else
-      hipLaunchKernelGGL(dy_load<float2>, dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n, 1,
-                         (const double2*)Vinv, (const float2*)P, g0, n_k);
-    st = gj_invert(Mw, Dinv, cnt, np, info, (int)g0, 1, s);
-    if (st != GW_OK) return st;
-    if (wt == GW_C128)
-      hipLaunchKernelGGL(dy_store<double2>, dim3(grid_elems((long long)n * n), cnt), dim3(256), 0, s, Mw, per, np,
-                         n, (const double2*)V, (double2*)W, g0, n_k);
-    else
-      hipLaunchKernelGGL(dy_store<float2>, dim3(grid_elems((long long)n * n), cnt), dim3(256), 0, s, Mw, per, np,
-                         n, (const double2*)V, (float2*)W, g0, n_k);
-  }
-  return check_launch("gw_screened_interaction");
+  if (prec == GW_FP64)
+    return screened_run<double2>(c, V, P, pt, W, wt, total, chunk, work, info, (hipStream_t)stream);
+  return screened_run<float2>(c, V, P, pt, W, wt, total, chunk, work, info, (hipStream_t)stream);
 }
 
 gw_status gw_green_dyson_workspace(const gw_cell* c, int chunk, size_t* bytes) {

@@ -38,7 +38,7 @@ def _inputs(cell, n_omega, seed):
     return V, P
 
 
-def _run(cell, V, P, pdt="c128", wdt="c128", chunk=None, in_place=False, info=None):
+def _run(cell, V, P, pdt="c128", wdt="c128", chunk=None, in_place=False, info=None, prec="fp64"):
     import torch
     import paper_1911_05633_amd as g
     tp = torch.complex128 if pdt == "c128" else torch.complex64
@@ -47,9 +47,9 @@ def _run(cell, V, P, pdt="c128", wdt="c128", chunk=None, in_place=False, info=No
     Pd = torch.from_numpy(np.ascontiguousarray(P)).to(tp).cuda()
     Wd = Pd if in_place else torch.empty(Pd.shape, dtype=tw, device="cuda")
     total = P.shape[0] * P.shape[1]
-    nb = g.gw_screened_interaction_workspace(cell, total if chunk is None else chunk)
+    nb = g.gw_screened_interaction_workspace(cell, total if chunk is None else chunk, prec)
     work = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    g.gw_screened_interaction(cell, Vd, Pd, Wd, work, info=info)
+    g.gw_screened_interaction(cell, Vd, Pd, Wd, work, info=info, prec=prec)
     torch.cuda.synchronize()
     return Wd.cpu().numpy()
 
@@ -66,6 +66,22 @@ def test_matches_oracle(name):
     W = _run(cell, V, P)
     ref = oracle.screened_interaction(V, P)
     assert _rel(W, ref) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["ragged", "si8"])
+def test_fp32_elimination(name):
+    """GW_FP32: both eliminations in FP32 on complex64 copies; bar 2e-5 normwise relative
+    (cond(V^-1 - P) below 1e2 here, FP32 rounding 6e-8)."""
+    print(f"[dyson] {name} fp32 elimination", flush=True)
+    cell = _cell(name)
+    V, P = _inputs(cell, 2, 8)
+    W = _run(cell, V, P, prec="fp32")
+    if name == "ragged":
+        assert _rel(W, oracle.screened_interaction(V, P)) < 2e-5
+    else:
+        for m, q in [(0, 0), (1, 33), (1, 63)]:
+            ref = oracle.screened_interaction(V[q:q + 1], P[m:m + 1, q:q + 1])[0, 0]
+            assert _rel(W[m, q], ref) < 2e-5, (m, q)
 
 
 def test_si8_sampled():
@@ -138,7 +154,7 @@ def test_argument_errors():
     def raw(w_ptr, p_type=g.GW_C128, w_type=g.GW_C128):
         return g.lib.gw_screened_interaction(cell.handle, ctypes.c_void_p(Vd.data_ptr()),
                                              ctypes.c_void_p(Pd.data_ptr()), p_type, ctypes.c_void_p(w_ptr), w_type,
-                                             2, ctypes.c_void_p(work.data_ptr()), work.numel(), None, None)
+                                             2, g.GW_FP64, ctypes.c_void_p(work.data_ptr()), work.numel(), None, None)
 
     assert raw(Pd.data_ptr() + 16) == g.GW_ERR_ARG                 # W overlaps P without being P
     assert raw(Pd.data_ptr(), g.GW_C128, g.GW_C64) == g.GW_ERR_ARG  # in place with two dtypes

@@ -289,7 +289,8 @@ gw_status gw_density_omega(const gw_cell* cell, const void* G, int n_omega, cons
  * through n_target there, else GW_ERR_ARG) until the electron count of the Dyson solution
  * (gw_green_dyson, then gw_density_omega) is within tol of n_target, or max_iter steps.  G (not
  * Sigma), work and n_dev are the caller's scratch; on return G holds the solution at *mu_out and
- * *n_out its count.  Synchronous: waits on `stream` once per step. */
+ * *n_out its count.  Synchronous: waits on `stream` once per step.  The Dyson solves inside do
+ * not report pivots; when Sigma may not be causal, check it first with gw_green_dyson's info. */
 gw_status gw_update_mu(const gw_cell* cell, const void* Hk, const void* Sigma, const void* Sigma_x, int n_omega,
                        double spin_factor, double n_target, double mu_lo, double mu_hi, double tol, int max_iter,
                        void* G, void* work, size_t work_size, double* n_dev, double* mu_out, double* n_out,

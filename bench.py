@@ -334,9 +334,14 @@ def pairs_bench(args, torch, log):
             return e0.elapsed_time(e1) / reps
 
         ms_cut, ms_dense = timed(cut), timed(dense)
+        plan = cell.pairs()
+        kept_elems = float((plan[:, 3].astype(np.int64) * plan[:, 4]).sum())   # sum over kept blocks of mA mB
+        dense_elems = float(spec.N_R) * spec.N_pb ** 2
         row = {"cell": kind, "atoms": spec.n_atoms, "N_R": spec.N_R, "n_tau": spec.n_tau, "kept_blocks": nk,
                "dense_blocks": spec.N_R * spec.n_atoms ** 2, "ms_cutoff": ms_cut, "ms_dense": ms_dense,
-               "us_per_kept_block_and_tau": ms_cut * 1e3 / (nk * spec.n_tau)}
+               "us_per_kept_block_and_tau": ms_cut * 1e3 / (nk * spec.n_tau),
+               "P_elements_per_tau_kept": kept_elems, "P_elements_per_tau_dense": dense_elems,
+               "storage_ratio_dense_over_kept": dense_elems / kept_elems}
         log(f"cutoff {kind}: {row}")
         rows.append(row)
         del d, cell

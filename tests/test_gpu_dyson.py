@@ -202,3 +202,32 @@ def test_closed_loop_p_w_sigma_fp64():
     WR = oracle.k_to_r(Wt, spec.mesh)
     S_ref = oracle.self_energy_r(oracle.k_to_r(Gk_h, spec.mesh), WR, spec, C)
     assert _rel(S.cpu().numpy(), S_ref) < 1e-9
+
+
+def test_oxide56_two_species_sampled():
+    """The 56-atom two-species cell (N_pb 3680, padded to 3712; 4 q): 2 frequencies, V and P formed
+    on the device from the seeded factors, two (q, nu) matrices against the oracle."""
+    import torch
+    import paper_1911_05633_amd as g
+    print("[dyson] oxide56 n=3680, 4 q, 2 nu", flush=True)
+    spec = sc.config(4)
+    cell = g.Cell.from_spec(spec, sc.coefficients(spec))
+    n, nk = cell.N_pb, cell.N_R
+    B, X, s = sc.dyson_factors(nk, n, 2, 12)
+    Bd = torch.from_numpy(B).cuda()
+    V = torch.matmul(Bd, Bd.conj().transpose(-1, -2).contiguous()) / n
+    V.diagonal(dim1=-2, dim2=-1).add_(0.5)
+    Xd = torch.from_numpy(X).cuda()
+    XX = torch.matmul(Xd, Xd.conj().transpose(-1, -2).contiguous()) / n
+    del Bd, Xd
+    P = torch.stack([-float(s[m]) * XX for m in range(2)]).contiguous()
+    W = torch.empty_like(P)
+    work = torch.empty(g.gw_screened_interaction_workspace(cell, 2 * nk), dtype=torch.uint8, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g.gw_screened_interaction(cell, V, P, W, work, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    Vh = V.cpu().numpy()
+    for m, q in [(0, 1), (1, 3)]:
+        ref = oracle.screened_interaction(Vh[q:q + 1], P[m:m + 1, q:q + 1].cpu().numpy())[0, 0]
+        assert _rel(W[m, q].cpu().numpy(), ref) < 1e-10, (m, q)

@@ -15,7 +15,7 @@ from tests import cells
 pytestmark = pytest.mark.gpu
 
 CASES = {"tiny": lambda: cells.tiny(complex_hopping=True), "two_species": lambda: cells.two_species(),
-         "si8": lambda: sc.config(2)}
+         "si8": lambda: sc.config(2), "oxide56": lambda: sc.config(4)}
 
 
 def _vr(spec):
@@ -25,7 +25,8 @@ def _vr(spec):
 
 
 @pytest.mark.parametrize("name,prec", [("tiny", "fp64"), ("two_species", "fp64"), ("si8", "fp64"),
-                                       ("si8", "fp32"), ("si8", "bf16x3")])
+                                       ("si8", "fp32"), ("si8", "bf16x3"), ("oxide56", "fp64"),
+                                       ("oxide56", "bf16x3")])
 def test_exchange_matches_oracle(name, prec):
     import torch
     import paper_1911_05633_amd as g

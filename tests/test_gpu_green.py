@@ -18,7 +18,7 @@ from tests import cells
 pytestmark = pytest.mark.gpu
 
 CASES = {"tiny": lambda: cells.tiny(complex_hopping=True), "two_species": lambda: cells.two_species(),
-         "si8": lambda: sc.config(2)}
+         "si8": lambda: sc.config(2), "oxide56": lambda: sc.config(4)}
 
 
 def _sigma(spec, n_om, seed):
@@ -52,7 +52,7 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("name", ["tiny", "two_species", "si8"])
+@pytest.mark.parametrize("name", ["tiny", "two_species", "si8", "oxide56"])
 def test_matches_oracle(name):
     import torch
     import paper_1911_05633_amd as g

@@ -94,3 +94,21 @@ def test_host_matsubara_matrix_has_the_declared_mirror_parity(kind, parity, n):
         T = g.gw_tau2omega_matrix(tau, g.matsubara(n + 3, beta, kind))
         mirror = parity * np.conj(T[:, ::-1])
         assert np.max(np.abs(T - mirror)) <= 1e-13 * np.max(np.abs(T))
+
+
+def test_next_row_entry_points_reject_a_null_cell_without_device():
+    import paper_1911_05633_amd as g
+    lib = g.lib
+    sz = ctypes.c_size_t()
+    mu, n = ctypes.c_double(), ctypes.c_double()
+    assert lib.gw_screened_interaction_workspace(None, 1, 0, ctypes.byref(sz)) == g.GW_ERR_ARG
+    assert lib.gw_green_dyson_workspace(None, 1, ctypes.byref(sz)) == g.GW_ERR_ARG
+    assert lib.gw_screened_interaction(None, None, None, 0, None, 0, 4, 0, None, 0, None, None) == g.GW_ERR_ARG
+    assert lib.gw_green_dyson(None, None, 0.0, 4, None, None, None, None, 0, None, None) == g.GW_ERR_ARG
+    assert lib.gw_density_omega(None, None, 4, None, None, 0.0, 2.0, None, None) == g.GW_ERR_ARG
+    assert lib.gw_update_mu(None, None, None, None, 4, 2.0, 8.0, -1.0, 1.0, 1e-9, 10, None, None, 0, None,
+                            ctypes.byref(mu), ctypes.byref(n), None) == g.GW_ERR_ARG
+    assert lib.gw_exchange(None, None, None, None, 0, None) == g.GW_ERR_ARG
+    assert lib.gw_polarizability_int(None, 8, None, None, None, None, None, None, 2.0, 0, None) == g.GW_ERR_ARG
+    assert lib.gw_self_energy_int(None, 8, None, None, None, None, None, None, None, None, None, 0, None) == g.GW_ERR_ARG
+    assert b"NULL" in lib.gw_last_error() or b"cell" in lib.gw_last_error()

@@ -534,7 +534,7 @@ def interstitial_bench(args, torch, log):
 def iteration_bench(args, torch, log):
     """One synthetic scGW iteration of the 72-atom cell on the device, stage by stage (HIP events):
     G(k, tau) -> G^R -> P (BF16 split) -> P(q, i nu) -> W~ (FP64 Dyson, all 48 nu x 8 q) -> W~(q, tau)
-    -> W~^R -> Sigma_c (BF16 split) -> Sigma_c(k, i w); Sigma_x; mu bisection over the G Dyson
+    -> W~^R -> Sigma_c (BF16 split) -> Sigma_c(k, i w); Sigma_x; mu search over the G Dyson
     solve (FP64).  Inputs: the seeded cell; V on-site (every q) = v_scale A, A Hermitian positive
     definite (synthcell.dyson_factors); a weak v_scale keeps the synthetic self-energy small
     enough for the tail-summed electron count."""
@@ -582,24 +582,10 @@ def iteration_bench(args, torch, log):
         Sx_stack[0].copy_(SxR)
         g.gw_fourier_r2k(cell, Sx_stack, Sx_stack, basis=0)
 
-    def count_at(mu):
-        g.gw_green_dyson(cell, Hk, mu, Gw, work_g, Sigma=S, Sigma_x=Sx_stack[0], info=info)
-        g.gw_density_omega(cell, Gw, Hk, mu, spec.spin, n_dev, Sigma_x=Sx_stack[0])
-        torch.cuda.synchronize()
-        return float(n_dev.item()), int(info.item())
-
     def mu_update():
-        target = spec.spin * no / 2.0
-        lo, hi = b.mu - 1.0, b.mu + 1.0
-        for _ in range(6):   # widen the bracket until it holds the target count
-            (n_lo, i_lo), (n_hi, i_hi) = count_at(lo), count_at(hi)
-            log(f"mu bracket [{lo:.3f}, {hi:.3f}]: counts {n_lo:.4f} .. {n_hi:.4f} (target {target}), "
-                f"pivot reports {i_lo}, {i_hi}")
-            if n_lo <= target <= n_hi:
-                break
-            lo, hi = lo - 2.0 * (hi - lo), hi + 2.0 * (hi - lo)
-        mu_box["mu"], mu_box["n"] = g.gw_update_mu(cell, Hk, Gw, work_g, n_dev, spec.spin, target, lo, hi,
-                                                  tol=1e-8, max_iter=60, Sigma=S, Sigma_x=Sx_stack[0])
+        mu_box["mu"], mu_box["n"] = g.gw_update_mu(cell, Hk, Gw, work_g, n_dev, spec.spin, spec.spin * no / 2.0,
+                                                  b.mu - 1.0, b.mu + 1.0, tol=1e-8, max_iter=60, Sigma=S,
+                                                  Sigma_x=Sx_stack[0])
 
     plan = [
         ("k2r G", lambda: g.gw_fourier_k2r(cell, Gk, GR, basis=0)),
@@ -614,7 +600,6 @@ def iteration_bench(args, torch, log):
         ("Sigma_x R->k", sx_k),
         ("mu + G Dyson", mu_update),
     ]
-    log(f"iteration {spec.name}: max |Sigma_c(k, i w)| follows the W stage")
     t0 = time.perf_counter()
     for name, fn in plan:
         a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -285,9 +285,10 @@ gw_status gw_green_dyson_workspace(const gw_cell* cell, int chunk, size_t* bytes
 gw_status gw_density_omega(const gw_cell* cell, const void* G, int n_omega, const void* Hk, const void* Sigma_x,
                            double mu, double spin_factor, double* n_dev, void* stream);
 
-/* Chemical-potential update (Sec. 4): bisection on mu in [mu_lo, mu_hi] (the count must rise
- * through n_target there, else GW_ERR_ARG) until the electron count of the Dyson solution
- * (gw_green_dyson, then gw_density_omega) is within tol of n_target, or max_iter steps.  G (not
+/* Chemical-potential update (Sec. 4): Illinois regula falsi (a bracketing secant) on mu in
+ * [mu_lo, mu_hi] (the count must rise through n_target there, else GW_ERR_ARG) until the
+ * electron count of the Dyson solution (gw_green_dyson, then gw_density_omega) is within tol of
+ * n_target, or max_iter steps.  G (not
  * Sigma), work and n_dev are the caller's scratch; on return G holds the solution at *mu_out and
  * *n_out its count.  Synchronous: waits on `stream` once per step.  The Dyson solves inside do
  * not report pivots; when Sigma may not be causal, check it first with gw_green_dyson's info. */

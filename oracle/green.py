@@ -8,8 +8,8 @@ frequency-dependent parts of the self-energy both included:
 
 The inverse is a library primitive (numpy.linalg.inv, LU with partial pivoting, FP64).
 
-The chemical-potential update (Sec. 4) bisects on mu: the electron count of the Dyson solution
-must match the target.  The count is the Matsubara sum of Tr G over the frequencies kept, with
+The chemical-potential update (Sec. 4) searches mu (Illinois regula falsi, a bracketing secant)
+until the electron count of the Dyson solution matches the target.  The count is the Matsubara sum of Tr G over the frequencies kept, with
 the 1 / (i w) and 1 / (i w)^2 tails of G summed in closed form (their coefficients are I and
 H - mu + Sigma_x).
 
@@ -68,27 +68,37 @@ def density_omega(G, Hk, mu, beta, g, Sigma_x=None):
 
 
 def update_mu(Hk, beta, n_omega, g, n_target, mu_lo, mu_hi, tol, max_iter, Sigma=None, Sigma_x=None):
-    """Chemical potential by bisection on the electron count of the Dyson solution.
+    """Chemical potential by the Illinois variant of regula falsi on the electron count of the
+    Dyson solution (a bracketing secant: the next mu interpolates the two bracket ends linearly,
+    and the end kept twice in a row has its count residual halved).
 
     The count rises with mu; the bracket must hold the target.  Each step solves Eq. (4) at the
-    midpoint and evaluates the count there; it stops when the count is within tol of the target
-    or after max_iter steps.  Returns (mu, count at mu)."""
+    new mu and evaluates the count there; it stops when the count is within tol of the target or
+    after max_iter steps.  Returns (mu, count at mu)."""
     om = fermionic_points(n_omega, beta)
 
-    def count(mu):
-        return density_omega(green_dyson(Hk, mu, om, Sigma, Sigma_x), Hk, mu, beta, g, Sigma_x)
+    def f(mu):
+        return density_omega(green_dyson(Hk, mu, om, Sigma, Sigma_x), Hk, mu, beta, g, Sigma_x) - n_target
 
     lo, hi = float(mu_lo), float(mu_hi)
-    if not (count(lo) <= n_target <= count(hi)):
+    f_lo, f_hi = f(lo), f(hi)
+    if not (f_lo <= 0.0 <= f_hi):
         raise ValueError("the bracket does not hold the target count")
-    mid, n_mid = lo, None
+    x, fx = lo, f_lo
+    side = 0
     for _ in range(max_iter):
-        mid = 0.5 * (lo + hi)
-        n_mid = count(mid)
-        if abs(n_mid - n_target) <= tol:
+        x = (lo * f_hi - hi * f_lo) / (f_hi - f_lo)
+        fx = f(x)
+        if abs(fx) <= tol:
             break
-        if n_mid < n_target:
-            lo = mid
+        if fx > 0.0:
+            hi, f_hi = x, fx
+            if side == -1:
+                f_lo *= 0.5
+            side = -1
         else:
-            hi = mid
-    return mid, n_mid
+            lo, f_lo = x, fx
+            if side == 1:
+                f_hi *= 0.5
+            side = 1
+    return x, fx + n_target

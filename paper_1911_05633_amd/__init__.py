@@ -418,8 +418,8 @@ def gw_density_omega(cell, G, Hk, mu, spin_factor, n_out, Sigma_x=None):
 
 def gw_update_mu(cell, Hk, G, work, n_dev, spin_factor, n_target, mu_lo, mu_hi, tol=1e-10, max_iter=100,
                  Sigma=None, Sigma_x=None):
-    """Bisection on mu; returns (mu, count).  G: complex128 [n_omega][N_k][N_orb][N_orb] scratch that
-    ends holding the Dyson solution at mu."""
+    """Regula falsi (Illinois) on mu; returns (mu, count).  G: complex128 [n_omega][N_k][N_orb][N_orb]
+    scratch that ends holding the Dyson solution at mu."""
     per = cell.N_R * cell.N_orb * cell.N_orb
     n_omega = G.numel() // per
     mu, n = ctypes.c_double(), ctypes.c_double()

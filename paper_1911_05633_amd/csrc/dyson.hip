@@ -546,22 +546,38 @@ gw_status gw_update_mu(const gw_cell* c, const void* Hk, const void* Sigma, cons
       return fail(GW_ERR_HIP, "reading the electron count failed");
     return GW_OK;
   };
+  // Illinois regula falsi on f(mu) = count(mu) - n_target: the next mu interpolates the bracket
+  // ends linearly; an end kept twice in a row has its residual halved (superlinear, bracketed)
   double lo = mu_lo, hi = mu_hi, n_lo = 0, n_hi = 0;
   gw_status st = count(lo, &n_lo);
   if (st != GW_OK) return st;
   st = count(hi, &n_hi);
   if (st != GW_OK) return st;
-  if (!(n_lo <= n_target && n_target <= n_hi)) return fail(GW_ERR_ARG, "the bracket does not hold the target count");
-  double mid = lo, n_mid = n_lo;
+  double f_lo = n_lo - n_target, f_hi = n_hi - n_target;
+  if (!(f_lo <= 0.0 && 0.0 <= f_hi)) return fail(GW_ERR_ARG, "the bracket does not hold the target count");
+  double x = lo, fx = f_lo;
+  int side = 0;
   for (int it = 0; it < max_iter; ++it) {
-    mid = 0.5 * (lo + hi);
-    st = count(mid, &n_mid);
+    x = (lo * f_hi - hi * f_lo) / (f_hi - f_lo);
+    double nx = 0;
+    st = count(x, &nx);
     if (st != GW_OK) return st;
-    if (std::fabs(n_mid - n_target) <= tol) break;
-    if (n_mid < n_target) lo = mid; else hi = mid;
+    fx = nx - n_target;
+    if (std::fabs(fx) <= tol) break;
+    if (fx > 0.0) {
+      hi = x;
+      f_hi = fx;
+      if (side == -1) f_lo *= 0.5;
+      side = -1;
+    } else {
+      lo = x;
+      f_lo = fx;
+      if (side == 1) f_hi *= 0.5;
+      side = 1;
+    }
   }
-  *mu_out = mid;
-  *n_out = n_mid;
+  *mu_out = x;
+  *n_out = fx + n_target;
   return GW_OK;
 }
 

@@ -231,3 +231,16 @@ def test_oxide56_two_species_sampled():
     for m, q in [(0, 1), (1, 3)]:
         ref = oracle.screened_interaction(Vh[q:q + 1], P[m:m + 1, q:q + 1].cpu().numpy())[0, 0]
         assert _rel(W[m, q].cpu().numpy(), ref) < 1e-10, (m, q)
+
+
+@pytest.mark.parametrize("n_pb,n_omega", [(64, 1), (128, 1), (1, 3)])
+def test_edge_sizes(n_pb, n_omega):
+    """One unpadded block, two unpadded blocks, and a 1 x 1 matrix padded to 64; a single frequency."""
+    import paper_1911_05633_amd as g
+    print(f"[dyson] edge n={n_pb} n_omega={n_omega}", flush=True)
+    C = np.zeros((n_pb, 1, 1))
+    C[:, 0, 0] = 1.0
+    cell = g.Cell([0], [1], [n_pb], [C], (2, 1, 1), 4, 10.0)
+    V, P = _inputs(cell, n_omega, 20 + n_pb)
+    W = _run(cell, V, P)
+    assert _rel(W, oracle.screened_interaction(V, P)) < 1e-10

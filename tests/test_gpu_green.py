@@ -177,3 +177,16 @@ def test_count_and_mu_update_match_oracle(name):
         g.gw_update_mu(cell, dev(Hk), Gs, work, n_dev, spec.spin, target, b.mu + 5.0, b.mu + 6.0,
                        Sigma=dev(S), Sigma_x=dev(Sx))
 
+
+
+def test_static_self_energy_only():
+    """Sigma = NULL with a Hermitian Sigma_x: G = [(i w + mu) - H - Sigma_x]^-1."""
+    import paper_1911_05633_amd as g
+    print("[green] Sigma_x only", flush=True)
+    spec = cells.two_species()
+    hop, b, Gk, C = cells.inputs(spec)
+    Hk = sc.hamiltonian_k(spec, hop)
+    cell = g.Cell.from_spec(spec, C)
+    _, Sx = _sigma(spec, 3, 11)
+    G = _run(cell, Hk, b.mu, 3, None, Sx)
+    assert _rel(G, oracle.green_dyson(Hk, b.mu, fermionic_points(3, spec.beta), Sigma_x=Sx)) < 1e-10

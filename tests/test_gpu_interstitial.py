@@ -27,6 +27,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("name,n_g,dtype", [("two_species", 37, "c128"), ("two_species", 37, "c64"),
+                                            ("two_species", 1, "c128"), ("two_species", 257, "c128"),
                                             ("si8", 64, "c128"), ("oxide56", 48, "c128")])
 def test_interstitial_blocks_match_oracle(name, n_g, dtype):
     import torch

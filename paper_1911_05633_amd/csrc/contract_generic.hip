@@ -217,9 +217,8 @@ static void p_generic_launch(const gw_cell* c, const SpeciesDev& A, const Specie
 }
 
 static void s_generic_launch(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
-                             const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s) {
-  const long long blocks = list ? (long long)c->n_tau * n
-                                : (long long)c->n_tau * c->N_R * A.atoms.size() * B.atoms.size();
+                             const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s, int nt) {
+  const long long blocks = list ? (long long)nt * n : (long long)nt * c->N_R * A.atoms.size() * B.atoms.size();
   if (blocks == 0) return;
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_generic<double2, double>), dim3((unsigned)blocks), dim3(256), 0, s, (const double2*)GR,
@@ -239,8 +238,8 @@ void launch_p_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesD
 }
 
 void launch_s_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
-                           const void* WR, void* S, gw_precision p, hipStream_t s) {
-  s_generic_launch(c, A, B, nullptr, 0, GR, WR, S, p, s);
+                           const void* WR, void* S, gw_precision p, hipStream_t s, int nt) {
+  s_generic_launch(c, A, B, nullptr, 0, GR, WR, S, p, s, nt);
 }
 
 void launch_p_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
@@ -250,7 +249,7 @@ void launch_p_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesD
 
 void launch_s_generic_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
                            const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s) {
-  if (n > 0) s_generic_launch(c, A, B, list, n, GR, WR, S, p, s);
+  if (n > 0) s_generic_launch(c, A, B, list, n, GR, WR, S, p, s, c->n_tau);
 }
 
 }  // namespace gwr

@@ -1399,8 +1399,8 @@ void launch_p_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
 }
 
 void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
-                        const void* WR, void* S, gw_precision p, hipStream_t s) {
-  const PairArgs q = make_args(c, A, B, c->n_tau);
+                        const void* WR, void* S, gw_precision p, hipStream_t s, int nt) {
+  const PairArgs q = make_args(c, A, B, nt);
   if (q.nblocks == 0) return;
   const unsigned threads = kSThreads;
   // s_mfma32 holds three workgroups per compute unit: two full rounds of them

@@ -9,12 +9,12 @@ namespace gwr {
 void launch_p_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
                            double g, gw_precision p, hipStream_t s);
 void launch_s_generic_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
-                           const void* WR, void* S, gw_precision p, hipStream_t s);
+                           const void* WR, void* S, gw_precision p, hipStream_t s, int nt);
 bool mfma_pair_ok(const SpeciesDev& A, const SpeciesDev& B);
 void launch_p_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
                         double g, gw_precision p, hipStream_t s);
 void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR,
-                        const void* WR, void* S, gw_precision p, hipStream_t s);
+                        const void* WR, void* S, gw_precision p, hipStream_t s, int nt);
 
 // GWR_KERNELS=generic selects the plain VALU kernels for every block shape; the tests
 // use it to check the matrix-core kernels against them on the device.
@@ -41,7 +41,8 @@ gw_status launch_polarizability(const gw_cell* c, const void* GR, void* P, doubl
 }
 
 gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, void* S, gw_precision p,
-                             hipStream_t s) {
+                             hipStream_t s, int n_tau) {
+  const int nt = n_tau < 0 ? c->n_tau : n_tau;
   // GW_BF16X3: split-precision BF16 kernel for the 9-orbital / 49..64-function species
   // pairs, the FP32 kernels for every other shape
   const bool gen = force_generic();
@@ -50,9 +51,9 @@ gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, v
       const SpeciesDev &A = c->sp[sa], &B = c->sp[sb];
       if (A.atoms.empty() || B.atoms.empty()) continue;
       if (!gen && mfma_pair_ok(A, B))
-        launch_s_mfma_pair(c, A, B, GR, WR, S, p, s);
+        launch_s_mfma_pair(c, A, B, GR, WR, S, p, s, nt);
       else
-        launch_s_generic_pair(c, A, B, GR, WR, S, p, s);
+        launch_s_generic_pair(c, A, B, GR, WR, S, p, s, nt);
     }
   return check_launch("self-energy");
 }

@@ -2,8 +2,9 @@
 // Eq. (8) after replacing the screening interaction by the bare one, W~(tau) -> V, and the Green's
 // function by -G(beta):
 //   Sigma_x^R_ab = -sum C^I_aa' (-G^R_a'b'(beta)) V^R_IJ C^J_bb'.
-// The self-energy kernels run on the single time slice tau = beta^- (a copy of the cell with one
-// time point) with V^R in place of W; the result is then negated, which applies the -G(beta).
+// The self-energy kernels run on the single time slice tau = beta^- (one time point from the
+// pointer to that slice) with V^R in place of W; the result is then negated, which applies the
+// -G(beta).
 #include "internal.h"
 
 namespace gwr {
@@ -39,11 +40,9 @@ extern "C" gw_status gw_exchange(const gw_cell* c, const void* GR, const void* V
   const size_t ng = (size_t)c->n_tau * slice, nv = (size_t)c->N_R * c->N_pb * c->N_pb;
   if (!disjoint(GR, ng * es, Sx, slice * 16) || !disjoint(VR, nv * es, Sx, slice * 16))
     return fail(GW_ERR_ARG, "Sigma_x overlaps an input");
-  gw_cell one = *c;   // the same cell with one time point: tau = beta^-
-  one.n_tau = 1;
   const char* g_beta = static_cast<const char*>(GR) + (size_t)(c->n_tau - 1) * slice * es;
   hipStream_t s = (hipStream_t)stream;
-  gw_status st = launch_self_energy(&one, g_beta, VR, Sx, prec, s);
+  gw_status st = launch_self_energy(c, g_beta, VR, Sx, prec, s, 1);
   if (st != GW_OK) return st;
   const long long n = (long long)slice;
   const long long blocks = (n + 255) / 256;

@@ -98,8 +98,9 @@ bool launch_p_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
                         const void* GR, void* P, double g, gw_precision p, hipStream_t s);
 bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
                         const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s);
+// n_tau < 0: the cell's time points; otherwise that many slices of GR and WR from the pointers given
 gw_status launch_self_energy(const gw_cell* c, const void* GR, const void* WR, void* S,
-                             gw_precision p, hipStream_t s);
+                             gw_precision p, hipStream_t s, int n_tau = -1);
 gw_status launch_density(const gw_cell* c, const void* G, gw_dtype t, int space, double g, double* n_dev,
                          hipStream_t s);
 

@@ -9,7 +9,8 @@
 //   per block step k (K = the 64 indices of block k), on M in place:
 //     D = M[K,K]^-1                     (one workgroup per matrix, LDS)
 //     M[K,J] = D M[K,J]          J != K (row panel)
-//     M[I,J] -= M[I,K] M[K,J]    I, J != K (rank-64 update, the bulk of the work)
+//     M[I,J] -= M[I,K] M[K,J]    I, J != K (rank-64 update, the bulk of the work, on the
+//                                           matrix cores)
 //     M[I,K] = -M[I,K] D         I != K (column panel);  M[K,K] = D
 // Matrices are padded to a multiple of 64 with the identity, whose inverse is itself.
 // Work: 8 n^3 real flops per inversion (n^3 complex multiply-adds).
@@ -226,9 +227,8 @@ __global__ __launch_bounds__(256) void dy_diag(MT* __restrict__ M, MT* __restric
   }
 }
 
-// 64 x 64 tile products of one block step (grid.z = matrix):
+// 64 x 64 panel products of one block step on the vector ALU (grid.z = matrix):
 //   OP 0: M[K,J] = D M[K,J]        (grid.x = J tile)
-//   OP 1: M[I,J] -= M[I,K] M[K,J]  (grid.x = J tile, grid.y = I tile)
 //   OP 2: M[I,K] = -M[I,K] D       (grid.x = I tile)
 // Thread (ty, tx) = (tid / 16, tid % 16) owns rows ty + 16 a and columns tx + 16 b of the tile.
 // A tile that is both read and written belongs to one workgroup, which reads all of it before
@@ -254,14 +254,6 @@ __global__ __launch_bounds__(256) void dy_tile(MT* __restrict__ M, const MT* __r
     B = Mc + K0 * np + (long long)J * kDB;
     ldb = np;
     C = Mc + K0 * np + (long long)J * kDB;
-  } else if (OP == 1) {
-    const int J = blockIdx.x, I = blockIdx.y;
-    if (I == k || J == k) return;
-    A = Mc + (long long)I * kDB * np + K0;
-    lda = np;
-    B = Mc + K0 * np + (long long)J * kDB;
-    ldb = np;
-    C = Mc + (long long)I * kDB * np + (long long)J * kDB;
   } else {
     const int I = blockIdx.x;
     if (I == k) return;
@@ -310,13 +302,120 @@ __global__ __launch_bounds__(256) void dy_tile(MT* __restrict__ M, const MT* __r
       MT* d = C + (long long)(ty + 16 * a) * np + tx + 16 * b;
       if (OP == 0) {
         *d = acc[a][b];
-      } else if (OP == 1) {
-        const MT v = *d;
-        *d = Cx<MT>::mk(v.x - acc[a][b].x, v.y - acc[a][b].y);
       } else {
         *d = Cx<MT>::mk(-acc[a][b].x, -acc[a][b].y);
       }
     }
+}
+
+// The rank-64 update M[I,J] -= M[I,K] M[K,J] of one block step on the matrix cores (16x16x4
+// real MFMAs in the element type; a complex product is four of them). Wavefront w owns the
+// 32 x 32 quadrant (w / 2, w % 2) of the 64 x 64 tile as 2 x 2 MFMA tiles with separate real
+// and imaginary accumulators. K is staged through LDS in steps of kKC as in dy_tile, and the
+// next stage is loaded into registers while the current one is multiplied. WPE caps the
+// wavefronts per SIMD so that the FP64 prefetch stays in registers (3 for complex128).
+typedef double dv4 __attribute__((ext_vector_type(4)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+template <class MT> struct Mx;
+template <> struct Mx<double2> {
+  typedef dv4 V;
+  static __device__ __forceinline__ dv4 op(double a, double b, dv4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output register j of lane group g (= lane / 16) holds row g + 4 j of the 16 x 16 tile
+  static __device__ __forceinline__ int row(int g, int j) { return g + 4 * j; }
+};
+template <> struct Mx<float2> {
+  typedef fv4 V;
+  static __device__ __forceinline__ fv4 op(float a, float b, fv4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int j) { return 4 * g + j; }
+};
+
+template <class MT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) void dy_update_mfma(MT* __restrict__ M, long long per, int np, int k) {
+  typedef Mx<MT> X;
+  typedef typename X::V V;
+  __shared__ MT As[kDB * (kKC + 1)];
+  __shared__ MT Bs[kKC * kDB];
+  const int J = blockIdx.x, I = blockIdx.y;
+  if (I == k || J == k) return;
+  const int c = blockIdx.z, tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  MT* Mc = M + (long long)c * per;
+  const long long K0 = (long long)k * kDB;
+  const MT* A = Mc + (long long)I * kDB * np + K0;
+  const MT* B = Mc + K0 * np + (long long)J * kDB;
+  MT* C = Mc + (long long)I * kDB * np + (long long)J * kDB;
+  V re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = V{0, 0, 0, 0};
+  typedef typename Cx<MT>::R R;
+  R par[4], pai[4], pbr[4], pbi[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = tid + 256 * r;
+    const MT a = A[(long long)(e >> 4) * np + (e & 15)], b = B[(long long)(e >> 6) * np + (e & 63)];
+    par[r] = a.x;
+    pai[r] = a.y;
+    pbr[r] = b.x;
+    pbi[r] = b.y;
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < kDB; k0 += kKC) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      As[(e >> 4) * (kKC + 1) + (e & 15)] = Cx<MT>::mk(par[r], pai[r]);
+      Bs[(e >> 6) * kDB + (e & 63)] = Cx<MT>::mk(pbr[r], pbi[r]);
+    }
+    __syncthreads();
+    if (k0 + kKC < kDB) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = tid + 256 * r;
+        const MT a = A[(long long)(e >> 4) * np + k0 + kKC + (e & 15)];
+        const MT b = B[(long long)(k0 + kKC + (e >> 6)) * np + (e & 63)];
+        par[r] = a.x;
+        pai[r] = a.y;
+        pbr[r] = b.x;
+        pbi[r] = b.y;
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < kKC / 4; ++ks) {
+      const int kk = 4 * ks + lk;
+      MT av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[(r0 + 16 * a + li) * (kKC + 1) + kk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk * kDB + c0 + 16 * b + li];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          re[a][b] = X::op(av[a].x, bv[b].x, re[a][b]);
+          re[a][b] = X::op(-av[a].y, bv[b].y, re[a][b]);
+          im[a][b] = X::op(av[a].x, bv[b].y, im[a][b]);
+          im[a][b] = X::op(av[a].y, bv[b].x, im[a][b]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        MT* d = C + (long long)(r0 + 16 * a + X::row(lk, j)) * np + c0 + 16 * b + li;
+        const MT v = *d;
+        *d = Cx<MT>::mk(v.x - re[a][b][j], v.y - im[a][b][j]);
+      }
 }
 
 unsigned grid_elems(long long n) {
@@ -333,7 +432,8 @@ gw_status gj_invert(MT* M, MT* Dinv, int count, int np, int* info, int code0, in
     hipLaunchKernelGGL(dy_diag<MT>, dim3(count), dim3(256), 0, s, M, Dinv, per, np, k, info, code0, sign);
     if (nt > 1) {
       hipLaunchKernelGGL((dy_tile<0, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
-      hipLaunchKernelGGL((dy_tile<1, MT>), dim3(nt, nt, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL((dy_update_mfma<MT, sizeof(MT) == 16 ? 3 : 8>), dim3(nt, nt, count), dim3(256), 0, s, M,
+                         per, np, k);
       hipLaunchKernelGGL((dy_tile<2, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
     }
   }

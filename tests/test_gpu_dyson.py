@@ -244,3 +244,39 @@ def test_edge_sizes(n_pb, n_omega):
     V, P = _inputs(cell, n_omega, 20 + n_pb)
     W = _run(cell, V, P)
     assert _rel(W, oracle.screened_interaction(V, P)) < 1e-10
+
+
+def test_si72_full_size_sampled():
+    """The 72-atom cell at full size (N_pb 4320, padded to 4352: 68 blocks; 8 q, one frequency),
+    inputs formed on the device as `bench.py --dyson` forms them; FP64 and FP32 eliminations.
+    Two (q, nu) matrices against the oracle (1e-10 and 2e-5), and Hermiticity of every FP64 output
+    (W~ is Hermitian because V and P are)."""
+    import torch
+    import paper_1911_05633_amd as g
+    print("[dyson] si72 full size n=4320, 8 q, 1 nu", flush=True)
+    spec = sc.config(3)
+    cell = g.Cell.from_spec(spec, sc.coefficients(spec))
+    n, nk = cell.N_pb, cell.N_R
+    B, X, s = sc.dyson_factors(nk, n, 1, 3)
+    Bd = torch.from_numpy(B).cuda()
+    V = torch.matmul(Bd, Bd.conj().transpose(-1, -2).contiguous()) / n
+    V.diagonal(dim1=-2, dim2=-1).add_(0.5)
+    del Bd, B
+    Xd = torch.from_numpy(X).cuda()
+    P = (torch.matmul(Xd, Xd.conj().transpose(-1, -2).contiguous()) * (-float(s[0]) / n)).unsqueeze(0).contiguous()
+    del Xd, X
+    W = torch.empty_like(P)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Vh = V.cpu().numpy()
+    refs = {q: oracle.screened_interaction(Vh[q:q + 1], P[0:1, q:q + 1].cpu().numpy())[0, 0] for q in (0, nk - 1)}
+    for prec, bar in (("fp64", 1e-10), ("fp32", 2e-5)):
+        work = torch.empty(g.gw_screened_interaction_workspace(cell, nk, prec), dtype=torch.uint8, device="cuda")
+        g.gw_screened_interaction(cell, V, P, W, work, info=info, prec=prec)
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0, prec
+        for q, ref in refs.items():
+            assert _rel(W[0, q].cpu().numpy(), ref) < bar, (prec, q)
+        if prec == "fp64":
+            herm = float((W - W.conj().transpose(-1, -2)).abs().max() / W.abs().max())
+            assert herm < 1e-10
+        del work

@@ -312,8 +312,9 @@ __global__ __launch_bounds__(256) void dy_tile(MT* __restrict__ M, const MT* __r
 // real MFMAs in the element type; a complex product is four of them). Wavefront w owns the
 // 32 x 32 quadrant (w / 2, w % 2) of the 64 x 64 tile as 2 x 2 MFMA tiles with separate real
 // and imaginary accumulators. K is staged through LDS in steps of kKC as in dy_tile, and the
-// next stage is loaded into registers while the current one is multiplied. WPE caps the
-// wavefronts per SIMD so that the FP64 prefetch stays in registers (3 for complex128).
+// next stage is loaded into registers while the current one is multiplied; the C tile is read
+// into registers before the K loop. WPE caps the wavefronts per SIMD so that all of it stays
+// in registers (2 for complex128, 4 for complex64).
 typedef double dv4 __attribute__((ext_vector_type(4)));
 typedef float fv4 __attribute__((ext_vector_type(4)));
 template <class MT> struct Mx;
@@ -355,6 +356,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) v
 #pragma unroll
     for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = V{0, 0, 0, 0};
   typedef typename Cx<MT>::R R;
+  R cr[2][2][4], ci[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const MT v = C[(long long)(r0 + 16 * a + X::row(lk, j)) * np + c0 + 16 * b + li];
+        cr[a][b][j] = v.x;
+        ci[a][b][j] = v.y;
+      }
   R par[4], pai[4], pbr[4], pbi[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -413,8 +425,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) v
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         MT* d = C + (long long)(r0 + 16 * a + X::row(lk, j)) * np + c0 + 16 * b + li;
-        const MT v = *d;
-        *d = Cx<MT>::mk(v.x - re[a][b][j], v.y - im[a][b][j]);
+        *d = Cx<MT>::mk(cr[a][b][j] - re[a][b][j], ci[a][b][j] - im[a][b][j]);
       }
 }
 
@@ -432,7 +443,7 @@ gw_status gj_invert(MT* M, MT* Dinv, int count, int np, int* info, int code0, in
     hipLaunchKernelGGL(dy_diag<MT>, dim3(count), dim3(256), 0, s, M, Dinv, per, np, k, info, code0, sign);
     if (nt > 1) {
       hipLaunchKernelGGL((dy_tile<0, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
-      hipLaunchKernelGGL((dy_update_mfma<MT, sizeof(MT) == 16 ? 3 : 8>), dim3(nt, nt, count), dim3(256), 0, s, M,
+      hipLaunchKernelGGL((dy_update_mfma<MT, sizeof(MT) == 16 ? 2 : 4>), dim3(nt, nt, count), dim3(256), 0, s, M,
                          per, np, k);
       hipLaunchKernelGGL((dy_tile<2, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
     }

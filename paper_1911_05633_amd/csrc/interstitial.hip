@@ -13,6 +13,9 @@ namespace {
 
 constexpr int kGT = 32;    // LDS transpose tile of the INT-INT polarizability
 constexpr int kCS = 4096;  // doubles of coefficients staged in LDS per pass (whole rows C^K)
+constexpr int kMxN = 9, kMxLd = 109;  // p_mixed_mx: orbitals; LDS row stride of C (9 x 12 + 1)
+// atoms whose P blocks with the grid run on the matrix cores (p_mixed_mx); the others on p_mixed
+__device__ __forceinline__ bool mx_species(int n, int m) { return n <= kMxN && m <= 64; }
 
 __device__ __forceinline__ double2 ld(const double2* p) { return *p; }
 __device__ __forceinline__ double2 ld(const float2* p) {
@@ -49,6 +52,7 @@ __global__ __launch_bounds__(256) void p_mixed(const T* __restrict__ Gog, const 
   const bool on = r < q.ng;
   const int tm = q.n_tau - 1 - tau, mR = q.minusR[R];
   const int s = q.species[t], n = q.n[s], m = q.m[s], o = q.orb_off[t], pb = q.pb_off[t];
+  if (mx_species(n, m)) return;  // p_mixed_mx covers this atom
   const double* C = q.C[s];
   const long long sl = (long long)q.No * q.ng;  // elements of one (tau, R) block of G_og or G_go
   double2 x[kMaxOrb], y[kMaxOrb];
@@ -99,6 +103,98 @@ __global__ __launch_bounds__(256) void p_mixed(const T* __restrict__ Gog, const 
         st(Pb + (long long)(pb + K) * q.ng + r, out);
       else
         st(Pb + (long long)r * q.Np + pb + K, out);
+    }
+  }
+}
+
+// The same blocks on the FP64 matrix cores for atoms with n <= 9 orbitals and m <= 64 product
+// functions.  Per atom and (tau, R) block, P[K][r] = -g sum_ab C^K_ab z_ab(r) with
+// z_ab(r) = x_a(r) y_b(r) is a real (m x n^2) by complex (n^2 x n_g) product: A = C^K_ab (K rows,
+// inner index 12 a + b, zero-padded to 64 x 108 in LDS), B = z (its real and imaginary parts as
+// two accumulations).  Wavefront w takes 16 grid points; lane (li, lk) takes the point r0 + li
+// and, in column group j, b = 4 j + lk, so it forms z from its own x_a and y_b in registers.
+// A workgroup stages C once and walks several (tau, R) blocks (grid.z stride).
+typedef double mxd4 __attribute__((ext_vector_type(4)));
+
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void p_mixed_mx(const T* __restrict__ Gog, const T* __restrict__ Ggo,
+                                                  T* __restrict__ P, double g, const IntArgs q) {
+  __shared__ double Cs[64 * kMxLd];
+  __shared__ double2 Xs[4 * kMxN * 16];
+  const int t = blockIdx.y, tid = threadIdx.x;
+  const int s = q.species[t], n = q.n[s], m = q.m[s], o = q.orb_off[t], pb = q.pb_off[t];
+  if (!mx_species(n, m)) return;  // p_mixed covers this atom
+  const double* C = q.C[s];
+  for (int i = tid; i < 64 * kMxLd; i += 256) {
+    const int K = i / kMxLd, ab = i - K * kMxLd, a = ab / 12, b = ab - a * 12;
+    Cs[i] = (K < m && a < n && b < n) ? C[((long long)K * n + a) * n + b] : 0.0;
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int r = blockIdx.x * 64 + 16 * w + li;
+  const bool on = r < q.ng;
+  const long long sl = (long long)q.No * q.ng, pl = (long long)q.Np * q.ng;
+  const int nblk = q.n_tau * q.NR;
+  for (int z = blockIdx.z; z < nblk; z += gridDim.z) {
+    const int tau = z / q.NR, R = z - tau * q.NR;
+    const int tm = q.n_tau - 1 - tau, mR = q.minusR[R];
+    double2 x[kMxN], y[kMxN];
+#pragma unroll
+    for (int a = 0; a < kMxN; ++a) {
+      x[a] = y[a] = make_double2(0.0, 0.0);
+      if (on && a < n) {
+        if (MODE == 0) {
+          x[a] = ld(Gog + ((long long)tau * q.NR + R) * sl + (long long)(o + a) * q.ng + r);
+          y[a] = ld(Ggo + ((long long)tm * q.NR + mR) * sl + (long long)r * q.No + o + a);
+        } else {
+          x[a] = ld(Ggo + ((long long)tau * q.NR + R) * sl + (long long)r * q.No + o + a);
+          y[a] = ld(Gog + ((long long)tm * q.NR + mR) * sl + (long long)(o + a) * q.ng + r);
+        }
+      }
+    }
+    // K index 12 a + b' with b' = 4 j + lk: this lane's y for the three column groups j
+    double2 ys[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      ys[j] = y[4 * j];
+#pragma unroll
+      for (int l = 1; l < 4; ++l)
+        if (lk == l) ys[j] = 4 * j + l < kMxN ? y[4 * j + l] : make_double2(0.0, 0.0);
+    }
+    mxd4 ar[4], ai[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ar[i] = ai[i] = mxd4{0, 0, 0, 0};
+    double2* Xw = Xs + w * kMxN * 16;  // this wavefront's x_a(r), [a][li]; read back by the same lanes
+#pragma unroll
+    for (int a = 0; a < kMxN; ++a) Xw[a * 16 + li] = x[a];  // the four lane groups write equal values
+#pragma unroll 1
+    for (int a = 0; a < n; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double2 xa = Xw[a * 16 + li];
+        const double zr = xa.x * ys[j].x - xa.y * ys[j].y, zi = xa.x * ys[j].y + xa.y * ys[j].x;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const double c = Cs[(16 * mt + li) * kMxLd + 12 * a + 4 * j + lk];
+          ar[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(c, zr, ar[mt], 0, 0, 0);
+          ai[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(c, zi, ai[mt], 0, 0, 0);
+        }
+      }
+    if (on) {
+      T* Pb = P + ((long long)tau * q.NR + R) * pl;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int K = 16 * mt + lk + 4 * j;  // FP64 MFMA output: register j of lane group lk is row lk + 4 j
+          if (K < m) {
+            const double2 out = make_double2(-g * ar[mt][j], -g * ai[mt][j]);
+            if (MODE == 0)
+              st(Pb + (long long)(pb + K) * q.ng + r, out);
+            else
+              st(Pb + (long long)r * q.Np + pb + K, out);
+          }
+        }
     }
   }
 }
@@ -270,11 +366,16 @@ gw_status gw_polarizability_int(const gw_cell* c, int ng, const void* Gog, const
   if (st != GW_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const dim3 gm((ng + 255) / 256, c->n_atoms, (unsigned)bl), gt((ng + kGT - 1) / kGT, (ng + kGT - 1) / kGT, (unsigned)bl);
+  const dim3 gx((ng + 63) / 64, c->n_atoms, (unsigned)(bl < 48 ? bl : 48));  // 48 WGs share C over the blocks
   if (t == GW_C128) {
+    hipLaunchKernelGGL((p_mixed_mx<double2, 0>), gx, dim3(256), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Ppg, g, q);
+    hipLaunchKernelGGL((p_mixed_mx<double2, 1>), gx, dim3(256), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Pgp, g, q);
     hipLaunchKernelGGL((p_mixed<double2, 0>), gm, dim3(256), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Ppg, g, q);
     hipLaunchKernelGGL((p_mixed<double2, 1>), gm, dim3(256), 0, s, (const double2*)Gog, (const double2*)Ggo, (double2*)Pgp, g, q);
     hipLaunchKernelGGL(p_gg<double2>, gt, dim3(256), 0, s, (const double2*)Ggg, (double2*)Pgg, g, q);
   } else {
+    hipLaunchKernelGGL((p_mixed_mx<float2, 0>), gx, dim3(256), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Ppg, g, q);
+    hipLaunchKernelGGL((p_mixed_mx<float2, 1>), gx, dim3(256), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Pgp, g, q);
     hipLaunchKernelGGL((p_mixed<float2, 0>), gm, dim3(256), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Ppg, g, q);
     hipLaunchKernelGGL((p_mixed<float2, 1>), gm, dim3(256), 0, s, (const float2*)Gog, (const float2*)Ggo, (float2*)Pgp, g, q);
     hipLaunchKernelGGL(p_gg<float2>, gt, dim3(256), 0, s, (const float2*)Ggg, (float2*)Pgg, g, q);

@@ -9,10 +9,10 @@
 //   per block step k (K = the 64 indices of block k), on M in place:
 //     D = M[K,K]^-1                     (one workgroup per matrix, LDS)
 //     M[K,J] = D M[K,J]          J != K (row panel)
-//     M[I,J] -= M[I,K] M[K,J]    I, J != K (rank-64 update, the bulk of the work, on the
-//                                           matrix cores)
+//     M[I,J] -= M[I,K] M[K,J]    I, J != K (rank-64 update, the bulk of the work)
 //     M[I,K] = -M[I,K] D         I != K (column panel);  M[K,K] = D
-// Matrices are padded to a multiple of 64 with the identity, whose inverse is itself.
+// Matrices are padded to a multiple of 64 with the identity, whose inverse is itself.  The three
+// tile products run on the matrix cores (dy_update_mfma).
 // Work: 8 n^3 real flops per inversion (n^3 complex multiply-adds).
 #include <cmath>
 #include <complex>
@@ -227,94 +227,18 @@ __global__ __launch_bounds__(256) void dy_diag(MT* __restrict__ M, MT* __restric
   }
 }
 
-// 64 x 64 panel products of one block step on the vector ALU (grid.z = matrix):
-//   OP 0: M[K,J] = D M[K,J]        (grid.x = J tile)
-//   OP 2: M[I,K] = -M[I,K] D       (grid.x = I tile)
-// Thread (ty, tx) = (tid / 16, tid % 16) owns rows ty + 16 a and columns tx + 16 b of the tile.
-// A tile that is both read and written belongs to one workgroup, which reads all of it before
-// the last barrier and writes after it.
-template <int OP, class MT>
-__global__ __launch_bounds__(256) void dy_tile(MT* __restrict__ M, const MT* __restrict__ Dinv,
-                                               long long per, int np, int k) {
-  typedef typename Cx<MT>::R R;
-  __shared__ MT As[kDB * (kKC + 1)];
-  __shared__ MT Bs[kKC * kDB];
-  const int c = blockIdx.z, tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  MT* Mc = M + (long long)c * per;
-  const MT* Dc = Dinv + (long long)c * kDB * kDB;
-  const long long K0 = (long long)k * kDB;
-  const MT *A, *B;
-  long long lda, ldb;
-  MT* C;
-  if (OP == 0) {
-    const int J = blockIdx.x;
-    if (J == k) return;
-    A = Dc;
-    lda = kDB;
-    B = Mc + K0 * np + (long long)J * kDB;
-    ldb = np;
-    C = Mc + K0 * np + (long long)J * kDB;
-  } else {
-    const int I = blockIdx.x;
-    if (I == k) return;
-    A = Mc + (long long)I * kDB * np + K0;
-    lda = np;
-    B = Dc;
-    ldb = kDB;
-    C = Mc + (long long)I * kDB * np + K0;
-  }
-  MT acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = Cx<MT>::mk(R(0), R(0));
-  for (int k0 = 0; k0 < kDB; k0 += kKC) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + 256 * r;
-      const int ai = e >> 4, ak = e & 15;
-      As[ai * (kKC + 1) + ak] = A[(long long)ai * lda + k0 + ak];
-      const int bk = e >> 6, bj = e & 63;
-      Bs[bk * kDB + bj] = B[(long long)(k0 + bk) * ldb + bj];
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < kKC; ++kk) {
-      MT av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[(ty + 16 * a) * (kKC + 1) + kk];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk * kDB + tx + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          acc[a][b].x = fma(av[a].x, bv[b].x, fma(-av[a].y, bv[b].y, acc[a][b].x));
-          acc[a][b].y = fma(av[a].x, bv[b].y, fma(av[a].y, bv[b].x, acc[a][b].y));
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      MT* d = C + (long long)(ty + 16 * a) * np + tx + 16 * b;
-      if (OP == 0) {
-        *d = acc[a][b];
-      } else {
-        *d = Cx<MT>::mk(-acc[a][b].x, -acc[a][b].y);
-      }
-    }
-}
-
-// The rank-64 update M[I,J] -= M[I,K] M[K,J] of one block step on the matrix cores (16x16x4
-// real MFMAs in the element type; a complex product is four of them). Wavefront w owns the
-// 32 x 32 quadrant (w / 2, w % 2) of the 64 x 64 tile as 2 x 2 MFMA tiles with separate real
-// and imaginary accumulators. K is staged through LDS in steps of kKC as in dy_tile, and the
-// next stage is loaded into registers while the current one is multiplied; the C tile is read
-// into registers before the K loop. WPE caps the wavefronts per SIMD so that all of it stays
-// in registers (2 for complex128, 4 for complex64).
+// The 64 x 64 tile products of one block step on the matrix cores (grid.z = matrix):
+//   OP 0: M[K,J] = D M[K,J]        (grid.x = J tile; row panel)
+//   OP 1: M[I,J] -= M[I,K] M[K,J]  (grid.x = J tile, grid.y = I tile; rank-64 update)
+//   OP 2: M[I,K] = -M[I,K] D       (grid.x = I tile; column panel)
+// 16x16x4 real MFMAs in the element type; a complex product is four of them. Wavefront w owns
+// the 32 x 32 quadrant (w / 2, w % 2) of the tile as 2 x 2 MFMA tiles with separate real and
+// imaginary accumulators. K is staged through LDS in steps of kKC, and the next stage is loaded
+// into registers while the current one is multiplied; for OP 1 the C tile is read into
+// registers before the K loop. A tile that is both read and written (OP 0, OP 2) belongs to one
+// workgroup, which has read all of it before the barrier that ends the K loop and writes after
+// it. WPE caps the wavefronts per SIMD so that everything stays in registers (2 for
+// complex128, 4 for complex64).
 typedef double dv4 __attribute__((ext_vector_type(4)));
 typedef float fv4 __attribute__((ext_vector_type(4)));
 template <class MT> struct Mx;
@@ -334,22 +258,47 @@ template <> struct Mx<float2> {
   static __device__ __forceinline__ int row(int g, int j) { return 4 * g + j; }
 };
 
-template <class MT, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) void dy_update_mfma(MT* __restrict__ M, long long per, int np, int k) {
+template <int OP, class MT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) void dy_update_mfma(
+    MT* __restrict__ M, const MT* __restrict__ Dinv, long long per, int np, int k) {
   typedef Mx<MT> X;
   typedef typename X::V V;
   __shared__ MT As[kDB * (kKC + 1)];
   __shared__ MT Bs[kKC * kDB];
-  const int J = blockIdx.x, I = blockIdx.y;
-  if (I == k || J == k) return;
   const int c = blockIdx.z, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
   MT* Mc = M + (long long)c * per;
+  const MT* Dc = Dinv + (long long)c * kDB * kDB;
   const long long K0 = (long long)k * kDB;
-  const MT* A = Mc + (long long)I * kDB * np + K0;
-  const MT* B = Mc + K0 * np + (long long)J * kDB;
-  MT* C = Mc + (long long)I * kDB * np + (long long)J * kDB;
+  const MT *A, *B;
+  long long lda, ldb;
+  MT* C;
+  if (OP == 0) {  // row panel: M[K,J] = D M[K,J]
+    const int J = blockIdx.x;
+    if (J == k) return;
+    A = Dc;
+    lda = kDB;
+    B = Mc + K0 * np + (long long)J * kDB;
+    ldb = np;
+    C = Mc + K0 * np + (long long)J * kDB;
+  } else if (OP == 1) {  // rank-64 update: M[I,J] -= M[I,K] M[K,J]
+    const int J = blockIdx.x, I = blockIdx.y;
+    if (I == k || J == k) return;
+    A = Mc + (long long)I * kDB * np + K0;
+    lda = np;
+    B = Mc + K0 * np + (long long)J * kDB;
+    ldb = np;
+    C = Mc + (long long)I * kDB * np + (long long)J * kDB;
+  } else {  // column panel: M[I,K] = -M[I,K] D
+    const int I = blockIdx.x;
+    if (I == k) return;
+    A = Mc + (long long)I * kDB * np + K0;
+    lda = np;
+    B = Dc;
+    ldb = kDB;
+    C = Mc + (long long)I * kDB * np + K0;
+  }
   V re[2][2], im[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -363,15 +312,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) v
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const MT v = C[(long long)(r0 + 16 * a + X::row(lk, j)) * np + c0 + 16 * b + li];
-        cr[a][b][j] = v.x;
-        ci[a][b][j] = v.y;
+        cr[a][b][j] = ci[a][b][j] = R(0);
+        if (OP == 1) {
+          const MT v = C[(long long)(r0 + 16 * a + X::row(lk, j)) * np + c0 + 16 * b + li];
+          cr[a][b][j] = v.x;
+          ci[a][b][j] = v.y;
+        }
       }
   R par[4], pai[4], pbr[4], pbi[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int e = tid + 256 * r;
-    const MT a = A[(long long)(e >> 4) * np + (e & 15)], b = B[(long long)(e >> 6) * np + (e & 63)];
+    const MT a = A[(long long)(e >> 4) * lda + (e & 15)], b = B[(long long)(e >> 6) * ldb + (e & 63)];
     par[r] = a.x;
     pai[r] = a.y;
     pbr[r] = b.x;
@@ -390,8 +342,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) v
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int e = tid + 256 * r;
-        const MT a = A[(long long)(e >> 4) * np + k0 + kKC + (e & 15)];
-        const MT b = B[(long long)(k0 + kKC + (e >> 6)) * np + (e & 63)];
+        const MT a = A[(long long)(e >> 4) * lda + k0 + kKC + (e & 15)];
+        const MT b = B[(long long)(k0 + kKC + (e >> 6)) * ldb + (e & 63)];
         par[r] = a.x;
         pai[r] = a.y;
         pbr[r] = b.x;
@@ -425,7 +377,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, WPE))) v
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         MT* d = C + (long long)(r0 + 16 * a + X::row(lk, j)) * np + c0 + 16 * b + li;
-        *d = Cx<MT>::mk(cr[a][b][j] - re[a][b][j], ci[a][b][j] - im[a][b][j]);
+        if (OP == 0)
+          *d = Cx<MT>::mk(re[a][b][j], im[a][b][j]);
+        else  // OP 1: C - A B (C read before the K loop); OP 2: -A B
+          *d = Cx<MT>::mk(cr[a][b][j] - re[a][b][j], ci[a][b][j] - im[a][b][j]);
       }
 }
 
@@ -442,10 +397,10 @@ gw_status gj_invert(MT* M, MT* Dinv, int count, int np, int* info, int code0, in
   for (int k = 0; k < nt; ++k) {
     hipLaunchKernelGGL(dy_diag<MT>, dim3(count), dim3(256), 0, s, M, Dinv, per, np, k, info, code0, sign);
     if (nt > 1) {
-      hipLaunchKernelGGL((dy_tile<0, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
-      hipLaunchKernelGGL((dy_update_mfma<MT, sizeof(MT) == 16 ? 2 : 4>), dim3(nt, nt, count), dim3(256), 0, s, M,
-                         per, np, k);
-      hipLaunchKernelGGL((dy_tile<2, MT>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      constexpr int wpe = sizeof(MT) == 16 ? 2 : 4;
+      hipLaunchKernelGGL((dy_update_mfma<0, MT, wpe>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL((dy_update_mfma<1, MT, wpe>), dim3(nt, nt, count), dim3(256), 0, s, M, Dinv, per, np, k);
+      hipLaunchKernelGGL((dy_update_mfma<2, MT, wpe>), dim3(nt, 1, count), dim3(256), 0, s, M, Dinv, per, np, k);
     }
   }
   return check_launch("screened interaction: elimination");

@@ -8,8 +8,8 @@ frequency-dependent parts of the self-energy both included:
 
 The inverse is a library primitive (numpy.linalg.inv, LU with partial pivoting, FP64).
 
-The chemical-potential update (Sec. 4) searches mu (Illinois regula falsi, a bracketing secant)
-until the electron count of the Dyson solution matches the target.  The count is the Matsubara sum of Tr G over the frequencies kept, with
+The chemical-potential update (Sec. 4) is the root of (electron count of the Dyson solution) minus
+the target, by bisection.  The count is the Matsubara sum of Tr G over the frequencies kept, with
 the 1 / (i w) and 1 / (i w)^2 tails of G summed in closed form (their coefficients are I and
 H - mu + Sigma_x).
 
@@ -68,37 +68,28 @@ def density_omega(G, Hk, mu, beta, g, Sigma_x=None):
 
 
 def update_mu(Hk, beta, n_omega, g, n_target, mu_lo, mu_hi, tol, max_iter, Sigma=None, Sigma_x=None):
-    """Chemical potential by the Illinois variant of regula falsi on the electron count of the
-    Dyson solution (a bracketing secant: the next mu interpolates the two bracket ends linearly,
-    and the end kept twice in a row has its count residual halved).
+    """Chemical potential (Sec. 4): the root in [mu_lo, mu_hi] of count(mu) - n_target, where count
+    is the electron count of the Dyson solution of Eq. (4) at mu, found by plain bisection.
 
-    The count rises with mu; the bracket must hold the target.  Each step solves Eq. (4) at the
-    new mu and evaluates the count there; it stops when the count is within tol of the target or
-    after max_iter steps.  Returns (mu, count at mu)."""
+    The count rises with mu; the bracket must hold the target (ValueError otherwise).  Each step
+    halves the bracket at its midpoint, solving Eq. (4) there; it stops when the count is within tol
+    of the target or after max_iter halvings.  Returns (mu, count at mu)."""
     om = fermionic_points(n_omega, beta)
 
-    def f(mu):
-        return density_omega(green_dyson(Hk, mu, om, Sigma, Sigma_x), Hk, mu, beta, g, Sigma_x) - n_target
+    def count(mu):
+        return density_omega(green_dyson(Hk, mu, om, Sigma, Sigma_x), Hk, mu, beta, g, Sigma_x)
 
     lo, hi = float(mu_lo), float(mu_hi)
-    f_lo, f_hi = f(lo), f(hi)
-    if not (f_lo <= 0.0 <= f_hi):
+    if not (count(lo) <= n_target <= count(hi)):
         raise ValueError("the bracket does not hold the target count")
-    x, fx = lo, f_lo
-    side = 0
+    mid, n_mid = lo, count(lo)
     for _ in range(max_iter):
-        x = (lo * f_hi - hi * f_lo) / (f_hi - f_lo)
-        fx = f(x)
-        if abs(fx) <= tol:
+        mid = 0.5 * (lo + hi)
+        n_mid = count(mid)
+        if abs(n_mid - n_target) <= tol:
             break
-        if fx > 0.0:
-            hi, f_hi = x, fx
-            if side == -1:
-                f_lo *= 0.5
-            side = -1
+        if n_mid > n_target:
+            hi = mid
         else:
-            lo, f_lo = x, fx
-            if side == 1:
-                f_hi *= 0.5
-            side = 1
-    return x, fx + n_target
+            lo = mid
+    return mid, n_mid

@@ -295,3 +295,33 @@ def test_electron_count_sign_and_spin():
     GR = oracle.k_to_r(Gk, spec.mesh)
     assert abs(oracle.electron_count(GR[-1, 0], 2.0) - spec.N_orb) < 1e-9
     assert abs(oracle.electron_count(GR[-1, 0], 1.0) - spec.N_orb / 2) < 1e-9
+
+
+def test_filon_fermionic_resolvent_tiny():
+    """T at the oracle's fermionic frequencies, applied to the band G(k, tau) of the tiny cell,
+    approaches the resolvent G(k, i w_n) = U (i w_n - (eps - mu))^-1 U^+ as h^2.  The closed form
+    needs exp(i w_n beta) = -1 (for other w the integral of -(1 - f) exp(-x tau) is
+    (1 - f)(1 - exp(-x beta)) / (i w - x) times a phase), so it pins the frequency set with T."""
+    errs = []
+    for n_tau in (101, 201):
+        spec = cells.tiny(n_tau=n_tau, beta=4.0, complex_hopping=True)
+        hop, b, Gk, C = cells.inputs(spec)
+        w = oracle.fermionic_frequencies(5, spec.beta)
+        Gw = oracle.apply_tau_to_omega(oracle.filon_matrix(sc.tau_grid(spec), w), Gk)  # [m][k][a][b]
+        x = b.eps - b.mu
+        ex = np.einsum("kan,mkn,kbn->mkab", b.U, 1.0 / (1j * w[:, None, None] - x[None]), np.conj(b.U))
+        errs.append(relmax(Gw, ex))
+    assert errs[0] < 1e-3
+    assert errs[0] / errs[1] > 3.5
+
+
+def test_bosonic_frequencies_annihilate_constants():
+    """A tau-independent function integrates to beta F at nu_0 and to zero at every other bosonic
+    frequency (exp(i nu_m beta) = 1); T is exact on constants, so this holds to rounding."""
+    beta = 6.5
+    tau = beta * np.arange(9) / 8
+    nu = oracle.bosonic_frequencies(6, beta)
+    Fw = oracle.filon_matrix(tau, nu) @ np.full(9, 0.3 - 0.1j)
+    assert abs(Fw[0] - beta * (0.3 - 0.1j)) < 1e-13
+    assert np.max(np.abs(Fw[1:])) < 1e-13
+    assert np.all(np.diff(nu) > 0) and nu[0] == 0.0

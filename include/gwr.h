@@ -63,8 +63,11 @@ typedef enum {
  *   GW_BF16X3 : storage as GW_FP32; in both contractions each FP32 operand is split into
  *               bf16 hi + lo and the products hi*hi + hi*lo + lo*hi run on the BF16 matrix
  *               cores with FP32 accumulation (relative error a few 1e-6; Sigma's FP64
- *               orbital sums as for GW_FP32).  Block shapes without such a kernel (species
- *               other than 9 orbitals with 49..64 product functions) run the FP32 kernels. */
+ *               orbital sums as for GW_FP32).  The split kernels cover species pairs of 9
+ *               orbitals with 49..64 product functions on both atoms.  Other pairs run what
+ *               GW_FP32 runs for them: the FP32 matrix-core kernels when both atoms have at
+ *               most 9 orbitals and 64 product functions, else the plain vector-ALU kernels
+ *               (FP32 operands, FP64 sums). */
 typedef enum { GW_FP64 = 0, GW_FP32 = 1, GW_BF16X3 = 2 } gw_precision;
 
 /* Storage type of a transform operand.  Transforms always compute in FP64. */
@@ -78,13 +81,32 @@ typedef struct gw_cell gw_cell;
  *   C: host FP64, species after species, each [n_pb[s]][n_orb[s]][n_orb[s]] holding
  *      <M_I | phi_a phi_b> (Eqs. (5), (8)); must be symmetric in (a, b) to 1e-12
  *      relative, else GW_ERR_ARG (the kernels fold that symmetry);
- *   mesh[3] >= 1 each; n_tau >= 2; beta > 0.
+ *   mesh[3] >= 1 each; 2 <= n_tau <= 256; beta > 0;
+ *   tau: host FP64 [n_tau], the imaginary-time grid on [0, beta] (Sec. 2: every function of
+ *      tau lives on [0, beta]).  It must start at 0 (standing for 0+), end at beta (beta-),
+ *      increase strictly and be symmetric about beta / 2: |tau_i + tau_{n_tau-1-i} - beta|
+ *      <= 1e-12 beta for every i, as must |tau_0| and |tau_{n_tau-1} - beta|.  Otherwise
+ *      GW_ERR_ARG before anything touches a device.  The mirror beta - tau_i is then the
+ *      index n_tau-1-i, which the polarizability's tau mirror, the parity pairing of the
+ *      drains and the beta^- slice of gw_density and gw_exchange rely on.  The grid is
+ *      copied; any such grid works (uniform, or clustered at both ends).
  * Limits: n_orb <= 16, n_pb <= 128, N_R <= 64 (GW_ERR_SHAPE beyond).
  * On success *out owns device memory until gw_cell_destroy. */
 gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom, int n_species,
                          const int* n_orb, const int* n_pb, const double* C, const int* mesh,
-                         int n_tau, double beta);
+                         int n_tau, double beta, const double* tau);
 void gw_cell_destroy(gw_cell* cell);
+
+/* The cell's tau grid, copied to the host buffer tau[n_tau].  GW_ERR_ARG for NULL. */
+gw_status gw_cell_tau(const gw_cell* cell, double* tau);
+
+/* Bytes of device scratch the path's calls (gw_fourier_k2r, gw_polarizability,
+ * gw_self_energy, gw_fourier_r2k, gw_tau2omega, gw_drain, gw_density and the _pairs
+ * variants) need for this cell at precision prec.  Every one of them keeps its temporaries
+ * in registers and LDS, so the answer is 0 for every cell and precision; callers that
+ * budget memory can rely on that.  The Dyson solves take their own workspace
+ * (gw_screened_interaction_workspace, gw_green_dyson_workspace). */
+size_t gw_workspace_bytes(const gw_cell* cell, gw_precision prec);
 
 /* Totals of a cell (0 for a NULL cell). */
 int gw_cell_n_orb_total(const gw_cell* cell);

@@ -26,7 +26,10 @@ PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "bf16x3": GW_BF16X3}
 _c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 _ip, _dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
-    "gw_cell_create": (_c_int, [ctypes.POINTER(_vp), _c_int, _ip, _c_int, _ip, _ip, _dp, _ip, _c_int, _c_double]),
+    "gw_cell_create": (_c_int, [ctypes.POINTER(_vp), _c_int, _ip, _c_int, _ip, _ip, _dp, _ip, _c_int, _c_double,
+                                _dp]),
+    "gw_cell_tau": (_c_int, [_vp, _dp]),
+    "gw_workspace_bytes": (ctypes.c_size_t, [_vp, _c_int]),
     "gw_cell_destroy": (None, [_vp]),
     "gw_cell_n_orb_total": (_c_int, [_vp]),
     "gw_cell_n_pb_total": (_c_int, [_vp]),
@@ -127,8 +130,11 @@ def _ptr(t, numel, name):
 class Cell:
     """Owns a gw_cell handle (constants on the current device)."""
 
-    def __init__(self, species_of_atom, n_orb, n_pb, C, mesh, n_tau, beta):
+    def __init__(self, species_of_atom, n_orb, n_pb, C, mesh, n_tau, beta, tau):
         species = np.ascontiguousarray(species_of_atom, dtype=np.int32)
+        tau = np.ascontiguousarray(tau, dtype=np.float64)
+        if tau.shape != (int(n_tau),):
+            raise ValueError(f"tau must hold n_tau = {n_tau} points")
         n_orb = np.ascontiguousarray(n_orb, dtype=np.int32)
         n_pb = np.ascontiguousarray(n_pb, dtype=np.int32)
         Cflat = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.float64).ravel() for c in C]))
@@ -136,7 +142,7 @@ class Cell:
         h = ctypes.c_void_p()
         st = lib.gw_cell_create(ctypes.byref(h), len(species), species.ctypes.data_as(_ip), len(n_orb),
                                 n_orb.ctypes.data_as(_ip), n_pb.ctypes.data_as(_ip), Cflat.ctypes.data_as(_dp),
-                                mesh.ctypes.data_as(_ip), int(n_tau), float(beta))
+                                mesh.ctypes.data_as(_ip), int(n_tau), float(beta), tau.ctypes.data_as(_dp))
         _check(st, "gw_cell_create")
         self.handle = h
         self.n_tau = int(n_tau)
@@ -147,8 +153,22 @@ class Cell:
         self.N_R = lib.gw_cell_n_R(h)
 
     @classmethod
-    def from_spec(cls, spec, C):
-        return cls(spec.species, spec.n_orb, spec.n_pb, C, spec.mesh, spec.n_tau, spec.beta)
+    def from_spec(cls, spec, C, tau=None):
+        """A cell from a description with the attributes species, n_orb, n_pb, mesh, n_tau, beta and
+        (unless tau is given) tau."""
+        return cls(spec.species, spec.n_orb, spec.n_pb, C, spec.mesh, spec.n_tau, spec.beta,
+                   spec.tau if tau is None else tau)
+
+    def tau(self):
+        """The cell's tau grid (host copy)."""
+        out = np.zeros(self.n_tau, dtype=np.float64)
+        _check(lib.gw_cell_tau(self.handle, out.ctypes.data_as(_dp)), "gw_cell_tau")
+        return out
+
+    def workspace_bytes(self, prec="fp64"):
+        """Device scratch of the path's calls for this cell (gw_workspace_bytes)."""
+        p = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        return int(lib.gw_workspace_bytes(self.handle, p))
 
     def n_basis(self, basis):
         return self.N_orb if basis == 0 else self.N_pb

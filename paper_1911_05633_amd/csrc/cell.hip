@@ -68,13 +68,26 @@ void gw_cell_destroy(gw_cell* cell) {
 
 gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom, int n_species,
                          const int* n_orb, const int* n_pb, const double* C, const int* mesh,
-                         int n_tau, double beta) {
+                         int n_tau, double beta, const double* tau) {
   if (!out) return fail(GW_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!species_of_atom || !n_orb || !n_pb || !C || !mesh) return fail(GW_ERR_ARG, "NULL input array");
+  if (!tau) return fail(GW_ERR_ARG, "tau grid is NULL");
   if (n_atoms < 1 || n_species < 1) return fail(GW_ERR_SHAPE, "need n_atoms >= 1 and n_species >= 1");
   if (n_tau < 2 || n_tau > 256) return fail(GW_ERR_SHAPE, "need 2 <= n_tau <= 256");
   if (!(beta > 0) || !std::isfinite(beta)) return fail(GW_ERR_ARG, "beta must be positive and finite");
+  // the grid runs from 0+ to beta- and is symmetric about beta / 2: the polarizability's mirror,
+  // the drains' parity pairing and the beta- slice of the density and the exchange rely on it
+  const double ttol = kTauTol * beta;
+  for (int i = 0; i < n_tau; ++i)
+    if (!std::isfinite(tau[i])) return fail(GW_ERR_ARG, "tau has a non-finite entry");
+  if (std::fabs(tau[0]) > ttol || std::fabs(tau[n_tau - 1] - beta) > ttol)
+    return fail(GW_ERR_ARG, "tau must start at 0 and end at beta");
+  for (int i = 0; i + 1 < n_tau; ++i)
+    if (!(tau[i + 1] > tau[i])) return fail(GW_ERR_ARG, "tau must be strictly increasing");
+  for (int i = 0; i < n_tau; ++i)
+    if (std::fabs(tau[i] + tau[n_tau - 1 - i] - beta) > ttol)
+      return fail(GW_ERR_ARG, "tau grid is not symmetric about beta / 2");
   for (int i = 0; i < 3; ++i)
     if (mesh[i] < 1) return fail(GW_ERR_SHAPE, "mesh entries must be >= 1");
   const int NR = mesh[0] * mesh[1] * mesh[2];
@@ -113,6 +126,7 @@ gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom,
   c->N_R = NR;
   c->n_tau = n_tau;
   c->beta = beta;
+  c->tau.assign(tau, tau + n_tau);
   c->minusR.resize(NR);
   for (int n1 = 0; n1 < mesh[0]; ++n1)
     for (int n2 = 0; n2 < mesh[1]; ++n2)
@@ -186,6 +200,20 @@ gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom,
     return fail(st, msg);
   }
   *out = c;
+  return GW_OK;
+}
+
+size_t gw_workspace_bytes(const gw_cell* c, gw_precision prec) {
+  // the hot-path calls keep every temporary in registers and LDS; prec is accepted for the
+  // signature's sake (no precision needs scratch either)
+  (void)c;
+  (void)prec;
+  return 0;
+}
+
+gw_status gw_cell_tau(const gw_cell* c, double* tau) {
+  if (!c || !tau) return fail(GW_ERR_ARG, "NULL pointer");
+  std::memcpy(tau, c->tau.data(), c->tau.size() * sizeof(double));
   return GW_OK;
 }
 

@@ -14,6 +14,7 @@ namespace gwr {
 constexpr int kMaxOrb = 16;
 constexpr int kMaxPb = 128;
 constexpr int kMaxR = 64;
+constexpr double kTauTol = 1e-12;  // relative to beta: end points and mirror symmetry of the tau grid
 constexpr int kMaxPairs = kMaxOrb * (kMaxOrb + 1) / 2;  // 136
 
 // Per-species device constants.
@@ -51,6 +52,7 @@ struct gw_cell {
   int N_R = 1;
   int n_tau = 0;
   double beta = 0;
+  std::vector<double> tau;             // host, the grid given at creation
   std::vector<int> minusR;             // host
   int* minusR_dev = nullptr;
   int* orb_off_dev = nullptr;

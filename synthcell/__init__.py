@@ -92,6 +92,11 @@ class CellSpec:
     def pb_off(self) -> np.ndarray:
         return np.concatenate([[0], np.cumsum(self.atom_npb)]).astype(np.int64)
 
+    @property
+    def tau(self) -> np.ndarray:
+        """The cell's imaginary-time grid (tau_grid)."""
+        return tau_grid(self)
+
     def seed(self) -> np.random.SeedSequence:
         return np.random.SeedSequence([ROOT_SEED, self.config_id, self.request_id])
 

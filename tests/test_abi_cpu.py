@@ -44,17 +44,18 @@ def test_validation_without_device():
     npb = np.array([16], dtype=np.int32)
     mesh = np.array([2, 2, 2], dtype=np.int32)
     C = np.zeros(16 * 16, dtype=np.float64)
+    tau8 = 10.0 * np.arange(8) / 7
     ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     # n_tau out of range, mesh entry 0, orbital count above the limit, bad species index
-    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(mesh), 1, 10.0) == g.GW_ERR_SHAPE
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(mesh), 1, 10.0, dp(tau8)) == g.GW_ERR_SHAPE
     bad_mesh = np.array([2, 0, 2], dtype=np.int32)
-    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(bad_mesh), 8, 10.0) == g.GW_ERR_SHAPE
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(bad_mesh), 8, 10.0, dp(tau8)) == g.GW_ERR_SHAPE
     big = np.array([17], dtype=np.int32)
-    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(big), ip(npb), dp(C), ip(mesh), 8, 10.0) == g.GW_ERR_SHAPE
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(big), ip(npb), dp(C), ip(mesh), 8, 10.0, dp(tau8)) == g.GW_ERR_SHAPE
     sp_bad = np.array([0, 3], dtype=np.int32)
-    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp_bad), 1, ip(no), ip(npb), dp(C), ip(mesh), 8, 10.0) == g.GW_ERR_ARG
-    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(mesh), 8, -1.0) == g.GW_ERR_ARG
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp_bad), 1, ip(no), ip(npb), dp(C), ip(mesh), 8, 10.0, dp(tau8)) == g.GW_ERR_ARG
+    assert lib.gw_cell_create(ctypes.byref(h), 2, ip(sp), 1, ip(no), ip(npb), dp(C), ip(mesh), 8, -1.0, dp(tau8)) == g.GW_ERR_ARG
     assert b"beta" in lib.gw_last_error()
 
 
@@ -112,3 +113,63 @@ def test_next_row_entry_points_reject_a_null_cell_without_device():
     assert lib.gw_polarizability_int(None, 8, None, None, None, None, None, None, 2.0, 0, None) == g.GW_ERR_ARG
     assert lib.gw_self_energy_int(None, 8, None, None, None, None, None, None, None, None, None, 0, None) == g.GW_ERR_ARG
     assert b"NULL" in lib.gw_last_error() or b"cell" in lib.gw_last_error()
+
+
+def _create_args():
+    import paper_1911_05633_amd as g
+    sp = np.zeros(2, dtype=np.int32)
+    no = np.array([4], dtype=np.int32)
+    npb = np.array([16], dtype=np.int32)
+    mesh = np.array([2, 2, 2], dtype=np.int32)
+    C = np.zeros(16 * 16, dtype=np.float64)
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return g, (ip(sp), ip(no), ip(npb), dp(C), ip(mesh)), dp, (sp, no, npb, C, mesh)
+
+
+@pytest.mark.parametrize("what", ["null", "start", "end", "order", "asymmetric", "nan"])
+def test_cell_create_refuses_a_bad_tau_grid_before_any_device_call(what):
+    """The tau grid must run from 0 to beta, increase and be symmetric about beta / 2: the
+    polarizability's mirror and the drains' parity pairing read index n-1-i as beta - tau_i."""
+    g, a, dp, keep = _create_args()
+    beta, n = 10.0, 8
+    tau = beta * np.arange(n) / (n - 1)
+    if what == "start":
+        tau[0] = 0.01
+    elif what == "end":
+        tau[-1] = beta - 0.01
+    elif what == "order":
+        tau[3], tau[4] = tau[4], tau[3]
+    elif what == "asymmetric":
+        tau[2] += 0.05  # increasing still, but no longer mirrored by tau[5]
+    elif what == "nan":
+        tau[2] = np.nan
+    h = ctypes.c_void_p()
+    ptr = None if what == "null" else dp(tau)
+    assert g.lib.gw_cell_create(ctypes.byref(h), 2, a[0], 1, a[1], a[2], a[3], a[4], n, beta, ptr) == g.GW_ERR_ARG
+    assert b"tau" in g.lib.gw_last_error()
+    assert not h.value
+
+
+@pytest.mark.parametrize("n", [2, 3, 48])
+def test_cell_create_grid_checks_pass_symmetric_grids(n):
+    """Uniform and clustered symmetric grids pass the tau checks: with them the call gets past the
+    validation and fails only where it first needs a device (no GPU here), or succeeds on one."""
+    g, a, dp, keep = _create_args()
+    beta = 37.0
+    for tau in (beta * np.arange(n) / (n - 1), 0.5 * beta * (1 - np.cos(np.pi * np.arange(n) / (n - 1)))):
+        h = ctypes.c_void_p()
+        st = g.lib.gw_cell_create(ctypes.byref(h), 2, a[0], 1, a[1], a[2], a[3], a[4], n, beta, dp(tau))
+        assert st in (g.GW_OK, g.GW_ERR_HIP), g.lib.gw_last_error()
+        if st == g.GW_OK:
+            g.lib.gw_cell_destroy(h)
+        else:
+            assert b"tau" not in g.lib.gw_last_error()
+
+
+def test_workspace_bytes_is_zero_for_the_path():
+    """The path's calls keep their temporaries on chip: no scratch for any precision."""
+    import paper_1911_05633_amd as g
+    for p in (g.GW_FP64, g.GW_FP32, g.GW_BF16X3):
+        assert g.lib.gw_workspace_bytes(None, p) == 0
+    assert g.lib.gw_cell_tau(None, None) == g.GW_ERR_ARG

@@ -28,7 +28,7 @@ def _cell(name):
     C[:, 0, 0] = 1.0
     C[:, 1, 1] = 0.5
     C[:, 0, 1] = C[:, 1, 0] = 0.25
-    return g.Cell([0] * n_atoms, [2], [n_pb], [C], mesh, 4, 10.0)
+    return g.Cell([0] * n_atoms, [2], [n_pb], [C], mesh, 4, 10.0, np.linspace(0.0, 10.0, 4))
 
 
 def _inputs(cell, n_omega, seed):
@@ -240,7 +240,7 @@ def test_edge_sizes(n_pb, n_omega):
     print(f"[dyson] edge n={n_pb} n_omega={n_omega}", flush=True)
     C = np.zeros((n_pb, 1, 1))
     C[:, 0, 0] = 1.0
-    cell = g.Cell([0], [1], [n_pb], [C], (2, 1, 1), 4, 10.0)
+    cell = g.Cell([0], [1], [n_pb], [C], (2, 1, 1), 4, 10.0, np.linspace(0.0, 10.0, 4))
     V, P = _inputs(cell, n_omega, 20 + n_pb)
     W = _run(cell, V, P)
     assert _rel(W, oracle.screened_interaction(V, P)) < 1e-10

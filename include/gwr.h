@@ -293,6 +293,20 @@ gw_status gw_screened_interaction_workspace(const gw_cell* cell, int chunk, gw_p
 gw_status gw_green_dyson(const gw_cell* cell, const void* Hk, double mu, int n_omega, const void* Sigma,
                          const void* Sigma_x, void* G, void* work, size_t work_size, int* info, void* stream);
 
+/* gw_green_dyson without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, result and kernels as gw_green_dyson; the scratch is a static 64 MiB device array
+ * inside the library (one per GPU, held until the process ends), so the call allocates nothing.
+ * A cell one of whose padded matrices needs more than 64 MiB (16 (No^2 + 4096) bytes,
+ * No = N_orb rounded up to 64, i.e. N_orb above 2040) is refused with GW_ERR_SHAPE before any
+ * launch; smaller cells are solved 64 MiB / (16 (No^2 + 4096)) matrices per launch.  Every call
+ * on one GPU uses that GPU's one array: calls that overlap in time on one GPU (on different
+ * streams or host threads) race and give undefined results.  Nothing in the array needs to
+ * start at zero (each launch writes what it reads); it keeps the last call's contents.
+ * The first call on a GPU looks up the array's device address there (no allocation). */
+gw_status gw_green_dyson_noalloc(const gw_cell* cell, const void* Hk, double mu, int n_omega, const void* Sigma,
+                                 const void* Sigma_x, void* G, int* info, void* stream);
+
 /* Workspace bytes of gw_green_dyson for `chunk` matrices per launch:
  * 16 * chunk * (No^2 + 4096), No = N_orb rounded up to 64. */
 gw_status gw_green_dyson_workspace(const gw_cell* cell, int chunk, size_t* bytes);

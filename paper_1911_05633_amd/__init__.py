@@ -54,6 +54,7 @@ SIGNATURES = {
     "gw_screened_interaction_workspace": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "gw_green_dyson": (_c_int, [_vp, _vp, _c_double, _c_int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "gw_green_dyson_workspace": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "gw_green_dyson_noalloc": (_c_int, [_vp, _vp, _c_double, _c_int, _vp, _vp, _vp, _vp, _vp]),
     "gw_density_omega": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _c_double, _c_double, _vp, _vp]),
     "gw_update_mu": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_double, _c_double, _c_double, _c_double, _c_double,
                               _c_int, _vp, _vp, ctypes.c_size_t, _vp, _dp, _dp, _vp]),
@@ -425,6 +426,32 @@ def gw_green_dyson(cell, Hk, mu, G, work, Sigma=None, Sigma_x=None, info=None):
                               None if Sigma_x is None else _ptr(Sigma_x, per, "Sigma_x"),
                               _ptr(G, G.numel(), "G"), ctypes.c_void_p(work.data_ptr()),
                               work.numel() * work.element_size(), ip, _stream()), "gw_green_dyson")
+
+
+GREEN_NOALLOC_SCRATCH_BYTES = 64 << 20  # the library's static scratch of gw_green_dyson_noalloc
+
+
+def gw_green_dyson_noalloc(cell, Hk, mu, G, Sigma=None, Sigma_x=None, info=None):
+    """gw_green_dyson with the library's static device scratch instead of a workspace argument
+    (for callers that cannot allocate); same arguments otherwise.  Calls that overlap in time
+    on one GPU race."""
+    torch = _torch()
+    per = cell.N_R * cell.N_orb * cell.N_orb
+    if G.numel() % per or G.numel() == 0:
+        raise ValueError("G must hold n_omega * N_k * N_orb^2 elements")
+    n_omega = G.numel() // per
+    for t, name in ((Hk, "Hk"), (G, "G"), (Sigma, "Sigma"), (Sigma_x, "Sigma_x")):
+        if t is not None and t.dtype != torch.complex128:
+            raise TypeError(f"{name} must be complex128")
+    ip = None
+    if info is not None:
+        if info.dtype != torch.int32 or info.numel() != 1:
+            raise ValueError("info must be a one-element int32 device tensor")
+        ip = _ptr(info, 1, "info")
+    _check(lib.gw_green_dyson_noalloc(cell.handle, _ptr(Hk, per, "Hk"), float(mu), n_omega,
+                                      None if Sigma is None else _ptr(Sigma, G.numel(), "Sigma"),
+                                      None if Sigma_x is None else _ptr(Sigma_x, per, "Sigma_x"),
+                                      _ptr(G, G.numel(), "G"), ip, _stream()), "gw_green_dyson_noalloc")
 
 
 def gw_density_omega(cell, G, Hk, mu, spin_factor, n_out, Sigma_x=None):

@@ -17,6 +17,8 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -529,19 +531,29 @@ gw_status gw_green_dyson_workspace(const gw_cell* c, int chunk, size_t* bytes) {
   return GW_OK;
 }
 
-gw_status gw_green_dyson(const gw_cell* c, const void* Hk, double mu, int n_omega, const void* Sigma,
-                         const void* Sigma_x, void* G, void* work, size_t work_size, int* info, void* stream) {
+}  // extern "C"
+
+namespace gwr {
+namespace {
+
+// Checks shared by the two G Dyson entry points: cell on the current device, pointers, sizes.
+gw_status green_common(const gw_cell* c, const void* Hk, const void* G, int n_omega, double mu) {
   if (!c) return fail(GW_ERR_ARG, "cell is NULL");
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return fail(GW_ERR_HIP, "hipGetDevice failed");
   if (cur != c->device) return fail(GW_ERR_ARG, "current device differs from the cell's device");
-  if (!Hk || !G || !work) return fail(GW_ERR_ARG, "NULL pointer");
+  if (!Hk || !G) return fail(GW_ERR_ARG, "NULL pointer");
   if (n_omega < 1) return fail(GW_ERR_SHAPE, "n_omega must be >= 1");
   if (!std::isfinite(mu)) return fail(GW_ERR_ARG, "mu must be finite");
+  return GW_OK;
+}
+
+// Operand overlaps against G and a workspace of bwork bytes, then the solve in chunks of
+// `chunk` matrices through that workspace.
+gw_status green_run(const gw_cell* c, const void* Hk, double mu, int n_omega, const void* Sigma,
+                    const void* Sigma_x, void* G, void* work, long long chunk, int* info, hipStream_t s) {
   const int n_k = c->N_R, n = c->N_orb, np = padded(n);
   const long long total = (long long)n_omega * n_k;
-  long long chunk = (long long)(work_size / green_bytes(np, 1));
-  if (chunk < 1) return fail(GW_ERR_SHAPE, "workspace smaller than gw_green_dyson_workspace(cell, 1)");
   if (chunk > total) chunk = total;
   if (chunk > 65535) chunk = 65535;
   const size_t nh = (size_t)n_k * n * n * 16, ng = (size_t)total * n * n * 16, bwork = green_bytes(np, chunk);
@@ -553,13 +565,14 @@ gw_status gw_green_dyson(const gw_cell* c, const void* Hk, double mu, int n_omeg
     return fail(GW_ERR_ARG, "Sigma and G must be the same tensor or disjoint");
   if (info && (!disjoint(info, 4, work, bwork) || !disjoint(info, 4, G, ng)))
     return fail(GW_ERR_ARG, "info overlaps an operand");
-  hipStream_t s = (hipStream_t)stream;
   const long long per = (long long)np * np;
   double2* Mw = static_cast<double2*>(work);
   double2* Dinv = Mw + chunk * per;
   if (info) hipLaunchKernelGGL(dy_zero_info, dim3(1), dim3(64), 0, s, info);
   for (long long g0 = 0; g0 < total; g0 += chunk) {
     const int cnt = (int)(total - g0 < chunk ? total - g0 : chunk);
+    // every element of the chunk's matrices (padding included) is written here, and the
+    // diagonal-block inverses by the elimination: the workspace needs no clearing
     hipLaunchKernelGGL(dy_load_green, dim3(grid_elems(per), cnt), dim3(256), 0, s, Mw, per, np, n,
                        (const double2*)Hk, (const double2*)Sigma_x, (const double2*)Sigma, mu, c->beta, g0, n_k);
     gw_status st = gj_invert(Mw, Dinv, cnt, np, info, (int)g0, 1, s);
@@ -568,6 +581,58 @@ gw_status gw_green_dyson(const gw_cell* c, const void* Hk, double mu, int n_omeg
                        (double2*)G, g0);
   }
   return check_launch("gw_green_dyson");
+}
+
+// Device scratch of gw_green_dyson_noalloc: one array per device, for callers that cannot
+// allocate.  In host code `scratch` only names the symbol; its device address on each GPU is
+// looked up once (hipGetSymbolAddress with that GPU current) and kept in scratch_ptr.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex scratch_mu;
+std::vector<void*> scratch_ptr;  // per device ordinal, nullptr until looked up
+
+gw_status scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (dev >= (int)scratch_ptr.size()) scratch_ptr.resize(dev + 1, nullptr);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GW_ERR_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return GW_OK;
+}
+
+}  // namespace
+}  // namespace gwr
+
+extern "C" {
+
+gw_status gw_green_dyson(const gw_cell* c, const void* Hk, double mu, int n_omega, const void* Sigma,
+                         const void* Sigma_x, void* G, void* work, size_t work_size, int* info, void* stream) {
+  gw_status st = green_common(c, Hk, G, n_omega, mu);
+  if (st != GW_OK) return st;
+  if (!work) return fail(GW_ERR_ARG, "NULL pointer");
+  const long long chunk = (long long)(work_size / green_bytes(padded(c->N_orb), 1));
+  if (chunk < 1) return fail(GW_ERR_SHAPE, "workspace smaller than gw_green_dyson_workspace(cell, 1)");
+  return green_run(c, Hk, mu, n_omega, Sigma, Sigma_x, G, work, chunk, info, (hipStream_t)stream);
+}
+
+gw_status gw_green_dyson_noalloc(const gw_cell* c, const void* Hk, double mu, int n_omega, const void* Sigma,
+                                 const void* Sigma_x, void* G, int* info, void* stream) {
+  gw_status st = green_common(c, Hk, G, n_omega, mu);
+  if (st != GW_OK) return st;
+  const size_t one = green_bytes(padded(c->N_orb), 1);
+  if (one > kStaticScratchBytes)
+    return fail(GW_ERR_SHAPE, "one matrix of this cell needs " + std::to_string(one) +
+                                  " bytes of scratch, above the 64 MiB static scratch of gw_green_dyson_noalloc");
+  void* work = nullptr;
+  st = scratch_address(c->device, &work);
+  if (st != GW_OK) return st;
+  return green_run(c, Hk, mu, n_omega, Sigma, Sigma_x, G, work, (long long)(kStaticScratchBytes / one), info,
+                   (hipStream_t)stream);
 }
 
 static double tail_sum(int n_om, double beta) {

@@ -3,6 +3,10 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--prec fp64|fp32|bf16x3]
     python bench.py --serve [--requests 200] [--slots 4]
 
+The step line also carries a bounded serving leg (--serve-requests, default 40 requests of the
+serving mix on the BF16-split path): its throughput and p50 / p99 latency beside the one-at-a-time
+FP64 service of the same stream.  Roofline entries are given per kernel and for the whole step.
+
 A step is the whole path on one synthetic cell with inputs resident in HBM:
     G(k,tau) -k2r-> G(R,tau) -> P (Eq. 5) and Sigma (Eq. 8, with W(R,tau))
     -> drain (R->k, tau->Matsubara) of P and of Sigma -> electron count.
@@ -146,38 +150,85 @@ def run_step(g, cell, d, spec, prec, ev=None):
             ev[i][1].record()
 
 
+# MFMA instructions per (tau, R, A, B) block of the BF16 split kernels on the 9-orbital /
+# 64-padded-function species pair (each 16x16x32, 16384 flop): the polarizability runs 84 per
+# wavefront on 4 wavefronts and evaluates the blocks of tau <= beta / 2 only (the mirror gives
+# the rest); the self-energy runs 84 per wavefront on 3 wavefronts for every block.
+MFMA_PER_BLOCK_BF16 = {"P": 4 * 84, "Sigma": 3 * 84}
+
+
 def kernel_roofs(spec, prec, fp, fs):
-    """Per kernel: (bound, algorithmic work per launch, peak, unit)."""
+    """Per kernel of the step: algorithmic flops and the peak they run against, algorithmic HBM
+    bytes (every operand read once, every result written once), executed flops where the kernel
+    runs a different count (BF16 split products, the tau mirror).  The roof of a kernel is
+    max(flops / peak, bytes / HBM peak)."""
     es = 16 if prec == "fp64" else 8
     No, Np, NR, nt = spec.N_orb, spec.N_pb, spec.N_R, spec.n_tau
-    peak_mfma = PEAK["fp64"] if prec == "fp64" else (PEAK["fp32"] if prec == "fp32" else PEAK["bf16"])
-    roofs = {}
-    roofs["k2r"] = ("hbm", nt * NR * No * No * (16 + es), HBM_PEAK)
-    roofs["P"] = ("mfma", fp * nt * NR, peak_mfma)
-    roofs["Sigma"] = ("mfma", fs * nt * NR, peak_mfma)
-    # drain: FP64 MFMA tau contraction (8 n_omega n_tau flop per column) vs in+out bytes
-    for name, n, e in (("drain_P", Np, es), ("drain_Sigma", No, 16)):
-        flops = 8.0 * nt * nt * NR * n * n
-        byts = 2.0 * nt * NR * n * n * e
-        roofs[name] = ("mfma", flops, PEAK["fp64"]) if flops / PEAK["fp64"] > byts / HBM_PEAK else ("hbm", byts, HBM_PEAK)
-    roofs["density"] = ("hbm", No * 16, HBM_PEAK)
-    return roofs
+    n_om, half = nt, (nt + 1) // 2
+    peak_mfma = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"], "bf16x3": PEAK["bf16"]}[prec]
+    gG, gP = float(nt * NR * No * No), float(nt * NR * Np * Np)
+    # R -> k: separable butterflies, N_R log2 N_R complex additions per (tau, element) column
+    dft = 2.0 * NR * np.log2(max(NR, 1))
+    k = {}
+    k["k2r"] = dict(flops=dft * gG / NR, peak=PEAK["fp64"], bytes=gG * (16 + es))
+    k["P"] = dict(flops=fp * nt * NR, peak=peak_mfma, bytes=gG * es + gP * es)
+    k["Sigma"] = dict(flops=fs * nt * NR, peak=peak_mfma, bytes=gG * es + gP * es + gG * 16)
+    # drain with the declared parity: per element and k, two real GEMMs of the n_omega x half
+    # matrices (Re T, Im T) on the paired complex columns u, v = y(tau) +- y(beta - tau):
+    # 8 n_omega half flop, plus the R -> k butterflies of u and v
+    for name, n2, e in (("drain_P", float(Np * Np), es), ("drain_Sigma", float(No * No), 16)):
+        k[name] = dict(flops=8.0 * n_om * half * NR * n2 + 2 * dft * half * n2, peak=PEAK["fp64"],
+                       bytes=2.0 * nt * NR * n2 * e)
+    k["density"] = dict(flops=float(NR * No), peak=PEAK["fp64"], bytes=float(NR * No * 16))
+    if prec == "bf16x3" and spec.n_species == 1 and spec.n_orb[0] == 9 and 48 < spec.n_pb[0] <= 64:
+        nb = float(NR * spec.n_atoms * spec.n_atoms)
+        k["P"]["executed_flops"] = MFMA_PER_BLOCK_BF16["P"] * 16384.0 * half * nb
+        k["Sigma"]["executed_flops"] = MFMA_PER_BLOCK_BF16["Sigma"] * 16384.0 * nt * nb
+    for v in k.values():
+        v["mfma_ms"] = v["flops"] / v["peak"] * 1e3
+        v["hbm_ms"] = v["bytes"] / HBM_PEAK * 1e3
+        v["bound"] = "mfma" if v["mfma_ms"] >= v["hbm_ms"] else "hbm"
+        v["roof_ms"] = max(v["mfma_ms"], v["hbm_ms"])
+    return k
 
 
-def oracle_sample(spec, d, log):
-    """The FP64 oracle on a bounded sample: P^q(tau) for one (tau, q) and Sigma^k(tau) for one
-    (tau, k) of the same cell.  Returns the slices and the CPU seconds spent on each."""
+def roofline_entries(roofs, per, prec, step_ms):
+    """Per-kernel roofline entries from the measured kernel times, and the whole step's."""
+    out = {}
+    for name, ms in per.items():
+        r = roofs[name]
+        if r["bound"] == "hbm":
+            achieved, peak, unit = r["bytes"] / (ms * 1e-3) / 1e9, HBM_PEAK / 1e9, "GB/s"
+        else:
+            achieved, peak, unit = r["flops"] / (ms * 1e-3) / 1e12, r["peak"] / 1e12, "TFLOP/s"
+        e = {"ms": ms, "bound": r["bound"], "achieved": achieved, "peak": peak, "unit": unit,
+             "frac": achieved / peak, "roof_ms": r["roof_ms"], "alg_flops": r["flops"], "alg_bytes": r["bytes"],
+             "mfma_roof_ms": r["mfma_ms"], "hbm_roof_ms": r["hbm_ms"], "traffic": traffic_for(name, prec)}
+        if "executed_flops" in r:
+            e["executed_flops"] = r["executed_flops"]
+            e["executed_mfma_ms"] = r["executed_flops"] / r["peak"] * 1e3
+        out[name] = e
+    roof = sum(roofs[n]["roof_ms"] for n in per)
+    return out, {"roof_ms": roof, "ms": step_ms, "frac": roof / step_ms,
+                 "kernel_ms_sum": float(sum(per.values()))}
+
+
+def oracle_sample(spec, d, log, n_slices=2):
+    """The FP64 oracle on a bounded sample: P^q(tau) and Sigma^k(tau) for n_slices (tau, q) pairs
+    of the same cell.  Returns the slices and the CPU seconds spent on each."""
     import oracle
-    t, q = spec.n_tau // 3, 1
-    t0 = time.perf_counter()
-    Pq = oracle.polarizability_q(d["Gk_h"], spec, d["C"], spec.spin, taus=[t], qs=[q])[0, 0]
-    tp = time.perf_counter() - t0
-    WR = {t: (d["et"][t] * d["sR"][:, None, None] * d["A"][None]).astype(np.complex128)}
-    t0 = time.perf_counter()
-    Sk = oracle.self_energy_k(d["Gk_h"], WR, spec, d["C"], taus=[t], ks=[q])[0, 0]
-    ts = time.perf_counter() - t0
-    log(f"cpu oracle sample: P {tp:.1f}s, Sigma {ts:.1f}s")
-    return dict(t=t, q=q, P=Pq, S=Sk, tp=tp, ts=ts)
+    tq = [(spec.n_tau // 3, 1), (spec.n_tau - 2, spec.N_R - 1)][:n_slices]
+    P, S, tp, ts = [], [], 0.0, 0.0
+    for t, q in tq:
+        t0 = time.perf_counter()
+        P.append(oracle.polarizability_q(d["Gk_h"], spec, d["C"], spec.spin, taus=[t], qs=[q])[0, 0])
+        tp += time.perf_counter() - t0
+        WR = {t: (d["et"][t] * d["sR"][:, None, None] * d["A"][None]).astype(np.complex128)}
+        t0 = time.perf_counter()
+        S.append(oracle.self_energy_k(d["Gk_h"], WR, spec, d["C"], taus=[t], ks=[q])[0, 0])
+        ts += time.perf_counter() - t0
+    log(f"cpu oracle sample ({len(tq)} slices): P {tp:.1f}s, Sigma {ts:.1f}s")
+    return dict(tq=tq, P=P, S=S, tp=tp, ts=ts)
 
 
 def slice_error(g, cell, d, spec, prec, smp, log):
@@ -189,11 +240,10 @@ def slice_error(g, cell, d, spec, prec, smp, log):
     g.gw_fourier_r2k(cell, d["P"], d["P"], basis=1)
     g.gw_fourier_r2k(cell, d["S"], d["S"], basis=0)
     torch.cuda.synchronize()
-    t, q = smp["t"], smp["q"]
-    Pg = d["P"][t, q].cpu().numpy().astype(np.complex128)
-    Sg = d["S"][t, q].cpu().numpy()
+    Pg = np.stack([d["P"][t, q].cpu().numpy().astype(np.complex128) for t, q in smp["tq"]])
+    Sg = np.stack([d["S"][t, q].cpu().numpy() for t, q in smp["tq"]])
     err = {}
-    for name, a, b in (("P", Pg, smp["P"]), ("Sigma", Sg, smp["S"])):
+    for name, a, b in (("P", Pg, np.stack(smp["P"])), ("Sigma", Sg, np.stack(smp["S"]))):
         mx = float(np.max(np.abs(a - b)))
         err[name] = {"max_abs": mx, "rel": mx / float(np.max(np.abs(b)))}
     log(f"{prec}: error vs oracle on the sampled slices: {err}")
@@ -201,18 +251,24 @@ def slice_error(g, cell, d, spec, prec, smp, log):
 
 
 def cpu_baseline(spec, smp, fp, fs):
-    """The oracle's sample as a rate: (its share of the step's algorithmic work) / CPU time."""
+    """The oracle's sample as a rate: (its share of the step's algorithmic work) / CPU time.
+    cores = the BLAS threads the oracle's numpy ran with (its only parallelism)."""
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
-    work = (fp + fs)  # one (tau, q) slice of P and of Sigma: 1 / (n_tau N_R) of the step each
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except Exception:
+        avail = os.cpu_count()
+    ns = len(smp["tq"])
+    work = ns * (fp + fs)  # each (tau, q) slice of P and of Sigma is 1 / (n_tau N_R) of the step's
     secs = smp["tp"] + smp["ts"]
     return {"value": work / secs / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"k-space FP64 oracle: P^q(tau) for 1 tau x 1 q and Sigma^k(tau) for 1 tau x 1 k of "
-                      f"the {spec.n_atoms}-atom cell (each a 1/{spec.n_tau * spec.N_R} share of the step's "
-                      f"P or Sigma output); {secs:.1f} s"}
+            "sample": f"k-space FP64 oracle: P^q(tau) and Sigma^k(tau) for {ns} (tau, q) pairs of the "
+                      f"{spec.n_atoms}-atom cell ({ns}/{spec.n_tau * spec.N_R} of the step's P and Sigma output), "
+                      f"{secs:.1f} s on {cores} BLAS threads ({avail} host cores available)"}
 
 
 def time_path(g, spec, prec, steps, warmup, torch, log):
@@ -237,11 +293,13 @@ def time_path(g, spec, prec, steps, warmup, torch, log):
     return d, cell, wall / steps * 1e3, per
 
 
-def serve_bench(args, torch, log):
-    """Serving mix: a seeded Poisson stream of independent P + Sigma requests over 2-, 8-, 24-,
-    40- and 72-atom cells with 16-48 tau points, served by the continuous-batching loop on
-    the mixed path; compared with one-at-a-time FP64 service of the same stream."""
+def serve_runs(n, slots, torch, log, prec="bf16x3"):
+    """Serving mix: a seeded stream of n independent P + Sigma requests over 2-, 8-, 24-, 40- and
+    72-atom cells with 16-48 tau points, served by the continuous-batching loop on the mixed path
+    (burst capacity, then Poisson arrivals at 0.7 of it: throughput, p50 / p99 latency), and the
+    same Poisson stream served one request at a time on the plain FP64 path."""
     import synthcell as sc
+    from synthcell.device import ServingInputs
     from paper_1911_05633_amd import serve
 
     def run(ex, reqs, slots):
@@ -254,7 +312,7 @@ def serve_bench(args, torch, log):
             raise RuntimeError(f"requests not served: {bad[:5]}")
         nerr = max(abs(r.result["n"] - r.result["n_expected"]) / r.result["n_expected"] for r in recs)
         s["max_electron_count_rel_err"] = nerr
-        return s, recs
+        return s
 
     def prepare(ex):
         t0 = time.perf_counter()
@@ -266,33 +324,41 @@ def serve_bench(args, torch, log):
         log(f"serving executor ({ex.prec}) prepared in {time.perf_counter() - t0:.1f}s, pool "
             f"{ex.capacity / 2**30:.1f} GiB")
 
-    n = args.requests
-    ex = serve.GWExecutor(prec="fp32", slots=args.slots)
+    inputs = ServingInputs()
+    ex = serve.GWExecutor(inputs, prec=prec, slots=slots)
     prepare(ex)
-    burst, _ = run(ex, sc.request_stream(n, rate=1.0, burst=True), args.slots)
+    burst = run(ex, sc.request_stream(n, rate=1.0, burst=True), slots)
     log(f"burst: {burst}")
     rate = 0.7 * burst["throughput_req_per_s"]
     reqs = sc.request_stream(n, rate=rate)
-    mixed, _ = run(ex, reqs, args.slots)
-    log(f"poisson at {rate:.2f} req/s (0.7 of the burst rate), mixed path: {mixed}")
+    mixed = run(ex, reqs, slots)
+    log(f"poisson at {rate:.2f} req/s (0.7 of the burst rate), {prec}: {mixed}")
     del ex
     torch.cuda.empty_cache()
-    ex64 = serve.GWExecutor(prec="fp64", slots=1)
+    ex64 = serve.GWExecutor(inputs, prec="fp64", slots=1)
     prepare(ex64)
-    base, _ = run(ex64, reqs, 1)
+    base = run(ex64, reqs, 1)
     log(f"same stream, one at a time, FP64: {base}")
     del ex64
     torch.cuda.empty_cache()
+    return {"requests": n, "slots": slots, "prec": prec, "rate_req_per_s": rate,
+            "throughput_req_per_s": mixed["throughput_req_per_s"], "p50_ms": mixed["p50_ms"],
+            "p99_ms": mixed["p99_ms"], "burst_capacity_req_per_s": burst["throughput_req_per_s"],
+            "poisson_mixed": mixed, "baseline_fp64_one_at_a_time": base,
+            "speedup_throughput_vs_baseline": mixed["throughput_req_per_s"] / base["throughput_req_per_s"],
+            "p99_ratio_baseline_over_mixed": base["p99_ms"] / mixed["p99_ms"],
+            "workload": f"{n} requests, Poisson arrivals at {rate:.3f} req/s (0.7 of the measured burst rate), "
+                        f"cells uniform over {list(sc.SERVING_KINDS)}, n_tau uniform over {list(sc.SERVING_NTAU)}"}
+
+
+def serve_bench(args, torch, log):
+    """The serving mix alone (bench.py --serve), as its own JSON line."""
+    r = serve_runs(args.requests, args.slots, torch, log)
     out = {
         "metric": "serving mix: P+Sigma requests/s with p50/p99 latency (continuous batching, mixed path)",
-        "value": mixed["throughput_req_per_s"], "unit": "req/s", "n_gpus": 1, "higher_is_better": True,
-        "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{n} requests, Poisson arrivals at {rate:.3f} req/s (0.7 of the measured burst "
-                               f"rate), cells uniform over {list(sc.SERVING_KINDS)}, n_tau uniform over "
-                               f"{list(sc.SERVING_NTAU)}", "slots": args.slots},
-        "burst_capacity": burst, "poisson_mixed": mixed, "baseline_fp64_one_at_a_time": base,
-        "speedup_throughput_vs_baseline": mixed["throughput_req_per_s"] / base["throughput_req_per_s"],
-        "p99_ratio_baseline_over_mixed": base["p99_ms"] / mixed["p99_ms"],
+        "value": r["throughput_req_per_s"], "unit": "req/s", "n_gpus": 1, "higher_is_better": True,
+        "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "dtype": "bf16x3+f64", "data": "synthetic",
+        "config": {"workload": r["workload"], "slots": args.slots}, "serving": r,
     }
     print(json.dumps(out), flush=True)
 
@@ -645,7 +711,9 @@ def main():
     ap.add_argument("--v-scale", type=float, default=1e-4, help="bare interaction scale of --iteration")
     ap.add_argument("--w-prec", default="fp64", choices=["fp64", "fp32"],
                     help="elimination precision of the W step in --iteration")
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=200, help="requests of --serve")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the bounded serving leg of the step benchmark (0: none)")
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -685,15 +753,14 @@ def main():
     d, cell, ms, per = time_path(g, spec, args.prec, args.steps, args.warmup, torch, log)
     total_flops = (fp + fs) * spec.n_tau * spec.N_R
     roofs = kernel_roofs(spec, args.prec, fp, fs)
+    entries, step_roof = roofline_entries(roofs, per, args.prec, ms)
     dom = max(per, key=per.get)
-    bound, work, peak = roofs[dom]
-    achieved = work / (per[dom] * 1e-3)
-    unit = "GB/s" if bound == "hbm" else "TFLOP/s"
-    scale = 1e9 if bound == "hbm" else 1e12
+    de = entries[dom]
     n_val = float(d["n"].cpu()[0])
     dtype = {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.prec]
     out = {
-        "metric": "P+Sigma GFLOP/s per scGW step (72-atom Si-like cell); frac of MFMA peak in roofline",
+        "metric": f"P+Sigma GFLOP/s per scGW step ({spec.n_atoms}-atom cell); frac of the kernels' rooflines; "
+                  f"p50/p99 latency of the serving mix",
         "value": total_flops / (ms * 1e-3) / 1e9,
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -708,8 +775,10 @@ def main():
         "config": {"workload": f"{spec.name}: {spec.n_atoms} atoms, n_orb {spec.n_orb}, n_pb {spec.n_pb}, "
                                f"mesh {'x'.join(map(str, spec.mesh))}, n_tau {spec.n_tau}, beta {spec.beta}",
                    "precision": args.prec, "per_kernel_ms": per, "electron_count": n_val},
-        "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / scale, "peak": peak / scale,
-                     "unit": unit, "frac": achieved / peak, "traffic": traffic_for(dom, args.prec)},
+        "roofline": {"kernel": dom, "bound": de["bound"], "achieved": de["achieved"], "peak": de["peak"],
+                     "unit": de["unit"], "frac": de["frac"], "traffic": de["traffic"]},
+        "roofline_per_kernel": entries,
+        "roofline_step": step_roof,
     }
     smp = None
     if not args.no_cpu:
@@ -731,6 +800,9 @@ def main():
             out["config"][f"{alt}_error_vs_oracle"] = slice_error(g, cella, da, spec, alt, smp, log)
         del da, cella
         torch.cuda.empty_cache()
+    if args.serve_requests > 0:
+        out["serving"] = serve_runs(args.serve_requests, args.slots, torch, log)
+        out["p50_ms"], out["p99_ms"] = out["serving"]["p50_ms"], out["serving"]["p99_ms"]
     print(json.dumps(out), flush=True)
 
 

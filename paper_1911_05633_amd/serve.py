@@ -266,23 +266,27 @@ def summarize(recs: Sequence[Record], makespan: Optional[float] = None) -> Dict:
 class GWExecutor:
     """Runs each request's whole path on its slot's stream, with buffers carved from one HBM pool.
 
-    Per request (prec "fp32" = mixed: complex64 G(R), W, P; FP32 matrix cores; FP64
-    transforms, Sigma sums and electron count; "fp64" = plain FP64):
-      G(k,tau) = -U diag((1 - f) e^{-x tau}) U^H     (input materialisation, torch)
-      W(R,tau) = A e^{-|R|/3} e^{-tau/5}              (input materialisation, torch)
+    Per request (prec "bf16x3" or "fp32" = mixed: complex64 G(R), W, P; BF16 split or FP32
+    matrix cores; FP64 transforms, Sigma sums and electron count; "fp64" = plain FP64):
+      the inputs G(k, tau) and W(R, tau), materialised on the slot's stream by the caller's
+      input provider (`inputs.materialize`), then
       gw_fourier_k2r, gw_polarizability, gw_self_energy, gw_drain (P, bosonic),
       gw_drain (Sigma, fermionic), gw_density.
-    Cells (per kind and n_tau), band data, C and A (per kind) are prepared once and
-    kept; only the pool's views change between requests.
+    The input provider also describes the cells: `inputs.spec(kind, n_tau)` (a description with
+    species, n_orb, n_pb, mesh, n_tau, beta, tau, spin, N_R, N_orb, N_pb), `inputs.kind_data(kind,
+    dtype)` (its "C" entry holds the product-basis coefficients) and `inputs.cell_data(spec,
+    dtype)`.  Cells and T matrices (per kind and n_tau) and the provider's data are prepared
+    once and kept; only the pool's views change between requests.
     """
 
-    def __init__(self, prec: str = "fp32", capacity: Optional[int] = None, headroom: int = 12 << 30,
+    def __init__(self, inputs, prec: str = "bf16x3", capacity: Optional[int] = None, headroom: int = 12 << 30,
                  slots: int = 4, keep: Sequence[str] = ()):
         import torch
-        import synthcell as sc
         from . import Cell, gw_tau2omega_matrix, matsubara
-        self.torch, self.sc = torch, sc
+        self.torch, self.inputs = torch, inputs
         self._Cell, self._T, self._mats = Cell, gw_tau2omega_matrix, matsubara
+        if prec not in ("fp64", "fp32", "bf16x3"):
+            raise ValueError(f"unknown precision {prec}")
         self.prec = prec
         self.keep = tuple(keep)
         if capacity is None:
@@ -296,40 +300,30 @@ class GWExecutor:
         self._cell: Dict[Tuple[str, int], Tuple] = {}
         self._t0 = None
 
+    def _cdt(self):
+        return self.torch.complex128 if self.prec == "fp64" else self.torch.complex64
+
     # -- preparation (host work done once per kind / per (kind, n_tau)) --
     def prepare_kind(self, kind: str):
-        if kind in self._kind:
-            return self._kind[kind]
-        torch, sc = self.torch, self.sc
-        spec = sc.serving_cell(kind, sc.SERVING_NTAU[0], 0)
-        b = sc.bands(spec, sc.hoppings(spec))
-        C = sc.coefficients(spec)
-        A = sc.w_amplitude(spec)
-        U = torch.from_numpy(b.U).cuda()
-        cdt = torch.complex128 if self.prec == "fp64" else torch.complex64
-        k = {"spec": spec, "C": C, "U": U, "Uh": U.conj().transpose(-1, -2).contiguous(),
-             "x": torch.from_numpy(b.eps - b.mu).cuda(), "A": torch.from_numpy(A).cuda().to(cdt)}
-        torch.cuda.synchronize()  # the slots' streams read these without further ordering
-        self._kind[kind] = k
-        return k
+        if kind not in self._kind:
+            self._kind[kind] = self.inputs.kind_data(kind, self._cdt())
+            self.torch.cuda.synchronize()  # the slots' streams read these without further ordering
+        return self._kind[kind]
 
     def prepare(self, req):
         key = (req.kind, req.n_tau)
         if key in self._cell:
             return self._cell[key]
-        torch, sc = self.torch, self.sc
+        torch = self.torch
         k = self.prepare_kind(req.kind)
-        spec = sc.serving_cell(req.kind, req.n_tau, 0)
+        spec = self.inputs.spec(req.kind, req.n_tau)
         cell = self._Cell.from_spec(spec, k["C"])
-        tau = sc.tau_grid(spec)
+        tau = spec.tau
         TP = torch.from_numpy(self._T(tau, self._mats(spec.n_tau, spec.beta, "bosonic"))).cuda()
         TS = torch.from_numpy(self._T(tau, self._mats(spec.n_tau, spec.beta, "fermionic"))).cuda()
-        sR, et = sc.w_factors(spec)
-        cdt = torch.complex128 if self.prec == "fp64" else torch.complex64
-        f = torch.from_numpy((et[:, None] * sR[None, :])).cuda().to(cdt)
-        tt = torch.from_numpy(tau).cuda()
+        cd = self.inputs.cell_data(spec, self._cdt())
         torch.cuda.synchronize()
-        self._cell[key] = (spec, cell, TP, TS, f, tt)
+        self._cell[key] = (spec, cell, TP, TS, cd)
         return self._cell[key]
 
     def _layout(self, spec) -> List[Tuple[str, Tuple[int, ...], object]]:
@@ -365,7 +359,7 @@ class GWExecutor:
     def launch(self, req, slot, offs):
         from . import gw_fourier_k2r, gw_polarizability, gw_self_energy, gw_drain, gw_density
         torch = self.torch
-        spec, cell, TP, TS, f, tt = self.prepare(req)
+        spec, cell, TP, TS, cd = self.prepare(req)
         k = self._kind[req.kind]
         t = {}
         for (name, shape, dt), off in zip(self._layout(spec), offs):
@@ -376,19 +370,7 @@ class GWExecutor:
         host_n = self.host_n[slot]  # read in finish(), before the slot takes another request
         with torch.cuda.stream(s):
             ev0.record()
-            # G(k, tau) = -U diag(g) U^H with g = (1 - f(x)) e^{-x tau}, exponents kept <= 0
-            x = k["x"][None]
-            tau = tt[:, None, None]
-            xp, xn = x.clamp(min=0), x.clamp(max=0)
-            gp = torch.exp(-xp * tau) / (1 + torch.exp(-xp * spec.beta))
-            gn = torch.exp(xn * (spec.beta - tau)) / (1 + torch.exp(xn * spec.beta))
-            mg = -torch.where(x >= 0, gp, gn)  # (n_tau, N_k, N_orb)
-            step = max(1, 8 // max(1, spec.N_R // 8))
-            for a in range(0, spec.n_tau, step):
-                b = min(spec.n_tau, a + step)
-                torch.matmul(k["U"][None] * mg[a:b, :, None, :].to(torch.complex128), k["Uh"][None],
-                             out=t["Gk"][a:b])
-            torch.mul(k["A"][None, None], f[:, :, None, None], out=t["W"])
+            self.inputs.materialize(k, cd, spec, t["Gk"], t["W"])
             # the path
             gw_fourier_k2r(cell, t["Gk"], t["GR"], basis=0)
             gw_polarizability(cell, t["GR"], t["P"], spec.spin, prec=self.prec)

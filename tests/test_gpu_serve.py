@@ -1,8 +1,8 @@
 """Serving on the GPU: requests that run together give the results they give alone.
 
 A burst of small requests is served with three slots (their work overlaps on the
-device); each request is then served alone.  P(q, i nu), Sigma(k, i omega) and the
-electron count must agree within the mixed path's tolerance (1e-5 relative, the
+device) on the BF16-split mixed path; each request is then served alone.  P(q, i nu),
+Sigma(k, i omega) and the electron count must agree within the mixed path's tolerance (1e-5 relative, the
 kernels being deterministic the difference is expected to be zero), the requests
 must have overlapped in time, and one request is checked against the FP64 oracle.
 """
@@ -26,7 +26,8 @@ def relmax(a, b):
 @pytest.fixture(scope="module")
 def executor():
     from paper_1911_05633_amd import serve
-    return serve.GWExecutor(prec="fp32", capacity=16 << 30, slots=3, keep=("P", "S"))
+    from synthcell.device import ServingInputs
+    return serve.GWExecutor(ServingInputs(), prec="bf16x3", capacity=16 << 30, slots=3, keep=("P", "S"))
 
 
 MIX = [Request(0, 0.0, "si24", 16), Request(1, 0.0, "tiny2", 16), Request(2, 0.0, "si8", 16),

@@ -1328,6 +1328,323 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   }
 }
 
+// ---------------------------------------------------------------------------
+// General block shapes (up to 16 orbitals and 128 product functions on either atom), on the
+// FP32 or FP64 matrix cores.  One workgroup of 8 wavefronts per compute unit walks a
+// contiguous range of blocks.
+//
+// Polarizability: the pair-folded form of p_mfma, P = -g C~_A Q C~_B^T, with Q (up to 144 x 144
+// pairs) formed and consumed 16 columns p' at a time so that it never has to sit in LDS whole:
+// per column chunk, Q[:, chunk] is formed from the G tiles, GEMM1 gives
+// D1[p'][I] = sum_p Q[p][p'] C~_A[I][p] (wavefront w: I tile w, K = np_pad(A)), and GEMM2
+// accumulates acc[J][I] += sum_{p' in chunk} C~_B[J][p'] D1[p'][I] from D1 in registers.
+// The tau mirror and the two stores are those of p_mfma; the direct block goes through a
+// per-wavefront LDS tile so that its rows leave as contiguous runs.
+// ---------------------------------------------------------------------------
+constexpr int kGPL = 144;           // padded pair count bound (16 orbitals: 136 pairs)
+constexpr int kGKA = kGPL / 4;      // GEMM1 K steps at most
+constexpr int kGMP = 128;           // padded product-function bound
+constexpr int kGJT = kGMP / 16;     // J tiles at most
+constexpr int kGS = 17;             // row stride (elements) of the 16-wide LDS chunks
+constexpr int kGThreads = 512;
+
+template <class RT, class CT>
+__global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT* __restrict__ P,
+                                                  const RT* __restrict__ CpA, const RT* __restrict__ CpB,
+                                                  const PairArgs q, double g) {
+  using M = Mma<RT>;
+  typedef typename M::cplx CR;
+  __shared__ CR Xs[kMaxOrb * kMaxOrb], Ys[kMaxOrb * kMaxOrb];
+  __shared__ CR Qc[kGPL * kGS];           // Q[p][p' - 16 c]
+  __shared__ RT Cb[kGMP * kGS];           // C~_B[J][p' - 16 c]
+  __shared__ CR Tt[8 * 16 * kGS];         // per wavefront: the direct block's 16 x 16 tile
+  __shared__ unsigned char ta[kMaxPairs], tb[kMaxPairs], tc[kMaxPairs], td[kMaxPairs];
+  __shared__ int mRs[kMaxR];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  for (int i = tid; i < q.npA; i += kGThreads) pair_of(i, q.nA, ta[i], tb[i]);
+  for (int i = tid; i < q.npB; i += kGThreads) pair_of(i, q.nB, tc[i], td[i]);
+  for (int i = tid; i < q.NR; i += kGThreads) mRs[i] = q.minusR[i];
+  const int nKA = q.nppA / 4, nCh = q.nppB / 16, nJT = (q.mB + 15) / 16;
+  const bool act = 16 * w < q.mA;  // this wavefront owns I tile w
+  // GEMM1 B operand: lane (k = lk, n = li) holds C~_A[I = 16 w + li][p = 4 ks + lk]; kept in
+  // registers for FP32, read from the (cache-resident) table at each use for FP64, whose
+  // accumulators leave no room for it
+  constexpr bool kRegB = sizeof(RT) == 4;
+  RT b1[kRegB ? kGKA : 1];
+  const RT* CpArow = CpA + (act ? (16 * w + li) * q.nppA : 0) + lk;
+  if constexpr (kRegB) {
+#pragma unroll
+    for (int ks = 0; ks < kGKA; ++ks) b1[ks] = (act && ks < nKA) ? CpArow[4 * ks] : RT(0);
+  }
+  const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+  CT xr, yr;
+  const bool xok = tid < q.nA * q.nB;
+  auto fetch = [&](const Blk& k) {
+    const int a = tid / q.nB, c = tid - a * q.nB;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
+    const int d = tid / q.nA, bb = tid - d * q.nA;
+    yr = ldraw(GR + ((long long)(q.n_tau - 1 - k.t) * q.NR + mRs[k.R]) * sl + (long long)(k.ob.y + d) * q.No +
+                   k.oa.y + bb,
+               GR, xok);
+  };
+  auto stage = [&]() {
+    if (xok) {
+      Xs[tid] = mk<RT>((double)xr.x, (double)xr.y);
+      Ys[tid] = mk<RT>((double)yr.x, (double)yr.y);
+    }
+  };
+  const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
+  const long long bbeg = (long long)blockIdx.x * per;
+  const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
+  Blk cur;
+  blk_start<false>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  blk_fill<false>(cur, q);
+  Blk nxt = cur;
+  blk_step<false>(nxt, q);
+  __syncthreads();  // pair tables and the minus-R table staged
+  if (bbeg < bend) {
+    fetch(cur);
+    stage();
+  }
+  __syncthreads();
+  for (long long blk = bbeg; blk < bend; ++blk) {
+    const Blk k = cur;
+    const int t = k.t, tm = q.n_tau - 1 - t, mR = mRs[k.R];
+    const int pA = k.oa.x, pB = k.ob.x;
+    const bool more = blk + 1 < bend;
+    if (more) {
+      blk_fill<false>(nxt, q);
+      fetch(nxt);
+    }
+    typename M::acc acc[kGJT][2];
+#pragma unroll
+    for (int Jt = 0; Jt < kGJT; ++Jt) acc[Jt][0] = acc[Jt][1] = typename M::acc{0, 0, 0, 0};
+    for (int ch = 0; ch < nCh; ++ch) {
+      // Q[p][16 ch + pc] (zero outside the live pairs) and the matching columns of C~_B
+      for (int i = tid; i < q.nppA * 16; i += kGThreads) {
+        const int p = i >> 4, pc = i & 15, pp = 16 * ch + pc;
+        RT qr = 0, qi = 0;
+        if (p < q.npA && pp < q.npB) {
+          const int a = ta[p], bq = tb[p], c = tc[pp], d = td[pp];
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int c1 = s2 ? d : c, d1 = s2 ? c : d;
+            if (s2 == 1 && c == d) break;
+            CR x = Xs[a * q.nB + c1], y = Ys[d1 * q.nA + bq];
+            qr += x.x * y.x - x.y * y.y;
+            qi += x.x * y.y + x.y * y.x;
+            if (a != bq) {
+              x = Xs[bq * q.nB + c1];
+              y = Ys[d1 * q.nA + a];
+              qr += x.x * y.x - x.y * y.y;
+              qi += x.x * y.y + x.y * y.x;
+            }
+          }
+        }
+        Qc[p * kGS + pc] = mk<RT>(qr, qi);
+      }
+      for (int i = tid; i < q.mpB * 16; i += kGThreads) {
+        const int J = i >> 4, pc = i & 15;
+        Cb[J * kGS + pc] = CpB[J * q.nppB + 16 * ch + pc];
+      }
+      __syncthreads();
+      if (act) {
+        // GEMM1: A = Q^T (row p' = li, k = p), two chains (Re Q, Im Q)
+        typename M::acc d1r = {0, 0, 0, 0}, d1i = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < kGKA; ++ks)
+          if (ks < nKA) {
+            const CR qv = Qc[(4 * ks + lk) * kGS + li];
+            RT bv;
+            if constexpr (kRegB)
+              bv = b1[ks];
+            else
+              bv = CpArow[4 * ks];
+            d1r = M::op(qv.x, bv, d1r);
+            d1i = M::op(qv.y, bv, d1i);
+          }
+        // GEMM2: K = p' of the chunk, step j takes row drow(lk, j) of D1 (register j)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int Jt = 0; Jt < kGJT; ++Jt)
+            if (Jt < nJT) {
+              const RT a = Cb[(16 * Jt + li) * kGS + M::drow(lk, j)];
+              acc[Jt][0] = M::op(a, d1r[j], acc[Jt][0]);
+              acc[Jt][1] = M::op(a, d1i[j], acc[Jt][1]);
+            }
+      }
+      __syncthreads();  // Qc and Cb are rewritten by the next chunk
+    }
+    // acc[Jt][part][j]: row J = 16 Jt + drow(lk, j), column I = 16 w + li; P_IJ = -g acc
+    if (act) {
+      CT* Pd = P + ((long long)t * q.NR + k.R) * slp;
+      CT* Pm = P + ((long long)tm * q.NR + mR) * slp;
+      const int I = 16 * w + li;
+      CR* Tw = Tt + w * 16 * kGS;
+#pragma unroll
+      for (int Jt = 0; Jt < kGJT; ++Jt)
+        if (Jt < nJT) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int Jl = M::drow(lk, j), J = 16 * Jt + Jl;
+            const double re = -g * (double)acc[Jt][0][j], im = -g * (double)acc[Jt][1][j];
+            Tw[li * kGS + Jl] = mk<RT>(re, im);
+            if (t != tm && I < q.mA && J < q.mB) stc(Pm + (long long)(pB + J) * q.Np + pA + I, re, im);
+          }
+          // the wavefront's own tile: lanes 16 r .. 16 r + 15 store row 4 e + r, 16 consecutive J
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = 4 * e + lk, J = 16 * Jt + li, Ir = 16 * w + r;
+            const CR v = Tw[r * kGS + li];
+            if (Ir < q.mA && J < q.mB) stc(Pd + (long long)(pA + Ir) * q.Np + pB + J, (double)v.x, (double)v.y);
+          }
+        }
+    }
+    if (more) stage();  // Xs, Ys were last read before the chunk loop's final barrier
+    cur = nxt;
+    blk_step<false>(nxt, q);
+    __syncthreads();
+  }
+}
+
+// Self-energy for the same general shapes, without the pair folding and its vector-ALU
+// unfold: the sum runs as three chained matrix products per chunk of 16 product functions J
+// of atom B,
+//   M[a'][J][b]  = sum_{b'} X[a'][b'] C^J_{b'b}                      (K = b')
+//   L^T[J][a]    = sum_I W[I][J] C^I_{a a'}          for each a'      (K = I)
+//   S^T[b][a]   += sum_J M[a'][J][b] L^T[J][a]       for each a'      (K = J, complex x complex)
+// (Eq. (8) with C symmetric in its orbital pair).  M goes through LDS, L^T stays in registers
+// (the D fragment of its product is the B operand of the next), the chunk of W is staged in
+// LDS with row loads.  Wavefront w owns the orbitals a' = w and a' = w + 8 of atom A and keeps
+// one accumulator per a'; the sum over a' and over the wavefronts is taken in FP64.
+// ---------------------------------------------------------------------------
+template <class RT, class CT>
+__global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, const CT* __restrict__ WR,
+                                                  double2* __restrict__ S, const RT* __restrict__ CA,
+                                                  const RT* __restrict__ CB, const PairArgs q) {
+  using M = Mma<RT>;
+  typedef typename M::cplx CR;
+  __shared__ CR Xs[kMaxOrb * kMaxOrb];     // X[a'][b'], 16 x 16 zero padded
+  __shared__ CR Ms[16 * 16 * kGS];         // M[a'][J - 16 c][b] (row stride kGS)
+  __shared__ CR Wc[kGMP * kGS];            // W[I][J - 16 c]
+  __shared__ double2 Sred[kMaxOrb * kMaxOrb];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int nA = q.nA, nB = q.nB, mA = q.mA, mB = q.mB;
+  const int nKI = q.mpA / 4, nCh = (mB + 15) / 16;
+  const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
+  // L's B operand: lane (k = lk, n = a = li) holds C^I_{a a'} for I = 4 ks + lk, per owned a'
+  auto ca = [&](int I, int a, int ap) -> RT {
+    return (I < mA && a < nA && ap < nA) ? CA[((long long)I * nA + a) * nA + ap] : RT(0);
+  };
+  const long long per_blk = (q.nblocks + gridDim.x - 1) / gridDim.x;
+  const long long bbeg = (long long)blockIdx.x * per_blk;
+  const long long bend = bbeg + per_blk < q.nblocks ? bbeg + per_blk : q.nblocks;
+  Blk cur;
+  blk_start<false>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  for (long long blk = bbeg; blk < bend; ++blk) {
+    blk_fill<false>(cur, q);
+    const Blk k = cur;
+    const CT* Gt = GR + ((long long)k.t * q.NR + k.R) * sl;
+    const CT* Wt = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)k.oa.x * q.Np + k.ob.x;
+    if (tid < 256) {
+      const int a = tid >> 4, c = tid & 15;
+      CR v = mk<RT>(0.0, 0.0);
+      if (a < nA && c < nB) {
+        const CT x = Gt[(long long)(k.oa.y + a) * q.No + k.ob.y + c];
+        v = mk<RT>((double)x.x, (double)x.y);
+      }
+      Xs[tid] = v;
+    }
+    typename M::acc sr[2], si[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) sr[u] = si[u] = typename M::acc{0, 0, 0, 0};
+    for (int ch = 0; ch < nCh; ++ch) {
+      const int J0 = 16 * ch;
+      // W[I][J0 .. J0 + 15] for every I: 16 consecutive elements of a row per 16 lanes
+      for (int i = tid; i < q.mpA * 16; i += kGThreads) {
+        const int I = i >> 4, Jl = i & 15;
+        CR v = mk<RT>(0.0, 0.0);
+        if (I < mA && J0 + Jl < mB) {
+          const CT x = Wt[(long long)I * q.Np + J0 + Jl];
+          v = mk<RT>((double)x.x, (double)x.y);
+        }
+        Wc[I * kGS + Jl] = v;
+      }
+      __syncthreads();  // Xs (first chunk) and Wc staged; Ms free
+      // M[a'][J][b] for J = J0 + 2 w, J0 + 2 w + 1: A = X (row a' = li, k = b'),
+      // B = C^J (k = b', n = b = li)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int Jl = 2 * w + h, J = J0 + Jl;
+        typename M::acc mr = {0, 0, 0, 0}, mi = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int bp = 4 * ks + lk;
+          const CR x = Xs[li * 16 + bp];
+          const RT cb = (J < mB && bp < nB && li < nB) ? CB[((long long)J * nB + bp) * nB + li] : RT(0);
+          mr = M::op(x.x, cb, mr);
+          mi = M::op(x.y, cb, mi);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Ms[(M::drow(lk, j) * 16 + Jl) * kGS + li] = mk<RT>((double)mr[j], (double)mi[j]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int ap = w + 8 * u;
+        if (ap < nA) {
+          // L^T[J][a] = sum_I W[I][J] C^I_{a a'}: A = W^T (row J = li, k = I), two chains
+          typename M::acc lr = {0, 0, 0, 0}, lim = {0, 0, 0, 0};
+          for (int ks = 0; ks < nKI; ++ks) {
+            const int I = 4 * ks + lk;
+            const CR wv = Wc[I * kGS + li];
+            const RT c = ca(I, li, ap);
+            lr = M::op(wv.x, c, lr);
+            lim = M::op(wv.y, c, lim);
+          }
+          // S^T[b][a] += sum_J M[a'][J][b] L^T[J][a]; step j: J = J0 + drow(lk, j)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const CR mv = Ms[(ap * 16 + M::drow(lk, j)) * kGS + li];
+            sr[u] = M::op(mv.x, lr[j], sr[u]);
+            sr[u] = M::op(-mv.y, lim[j], sr[u]);
+            si[u] = M::op(mv.x, lim[j], si[u]);
+            si[u] = M::op(mv.y, lr[j], si[u]);
+          }
+        }
+      }
+      __syncthreads();  // Wc and Ms are rewritten by the next chunk
+    }
+    // S_ab = -sum over a' of the accumulators (row b = drow(lk, j), column a = li), in FP64
+    for (int i = tid; i < 256; i += kGThreads) Sred[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int r = 0; r < 8; ++r) {
+      if (w == r) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (w + 8 * u < nA)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              double2& s = Sred[li * 16 + M::drow(lk, j)];
+              s.x += (double)sr[u][j];
+              s.y += (double)si[u][j];
+            }
+      }
+      __syncthreads();
+    }
+    if (tid < 256) {
+      const int a = tid >> 4, b = tid & 15;
+      if (a < nA && b < nB) {
+        const double2 v = Sred[tid];
+        S[((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + b] = make_double2(-v.x, -v.y);
+      }
+    }
+    blk_step<false>(cur, q);
+    __syncthreads();  // Xs and Sred are rewritten by the next block
+  }
+}
+
 PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, int n_half) {
   PairArgs q;
   q.nA = A.n;
@@ -1490,4 +1807,34 @@ bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
   return true;
 }
 
+// General shapes on the matrix cores (one workgroup of 8 wavefronts per compute unit).
+void launch_p_mfma_gen(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, void* P,
+                       double g, gw_precision p, hipStream_t s) {
+  const PairArgs q = make_args(c, A, B, (c->n_tau + 1) / 2);
+  if (q.nblocks == 0) return;
+  const unsigned grid = (unsigned)(q.nblocks < c->n_cu ? q.nblocks : c->n_cu);
+  if (p == GW_FP64)
+    hipLaunchKernelGGL((p_mfma_gen<double, double2>), dim3(grid), dim3(kGThreads), 0, s, (const double2*)GR,
+                       (double2*)P, A.Cpair, B.Cpair, q, g);
+  else
+    hipLaunchKernelGGL((p_mfma_gen<float, float2>), dim3(grid), dim3(kGThreads), 0, s, (const float2*)GR,
+                       (float2*)P, A.Cpair32, B.Cpair32, q, g);
+}
+
+void launch_s_mfma_gen(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const void* GR, const void* WR,
+                       void* S, gw_precision p, hipStream_t s, int nt) {
+  const PairArgs q = make_args(c, A, B, nt);
+  if (q.nblocks == 0) return;
+  // FP32: two workgroups fit a compute unit (registers and LDS), FP64 one
+  const long long cap = (long long)(p == GW_FP64 ? 1 : 2) * c->n_cu;
+  const unsigned grid = (unsigned)(q.nblocks < cap ? q.nblocks : cap);
+  if (p == GW_FP64)
+    hipLaunchKernelGGL((s_mfma_gen<double, double2>), dim3(grid), dim3(kGThreads), 0, s, (const double2*)GR,
+                       (const double2*)WR, (double2*)S, A.C, B.C, q);
+  else
+    hipLaunchKernelGGL((s_mfma_gen<float, float2>), dim3(grid), dim3(kGThreads), 0, s, (const float2*)GR,
+                       (const float2*)WR, (double2*)S, A.C32, B.C32, q);
+}
+
 }  // namespace gwr
+

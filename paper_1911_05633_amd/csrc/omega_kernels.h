@@ -741,10 +741,16 @@ template <class TI, class TO>
 gw_status drain_typed(const gw_cell* c, const double2* T, int n_omega, int parity, const TI* in, TO* out, int n,
                       gw_dtype ot, hipStream_t s) {
   const long long n2 = (long long)n * n;
-  if (mfma_ok(c->n_tau, n_omega) && drain_dispatch(c, T, n_omega, parity, in, out, n2, s))
+  // two passes through `out` (R -> k, then tau -> omega over N_R n^2 columns) need room for
+  // n_tau rows there: in place, or n_omega >= n_tau
+  const bool two_pass_ok = (const void*)in == (const void*)out || n_omega >= c->n_tau;
+  // A fused pass keeps whole (tau, element) columns of N_R values per thread only up to N_R = 16;
+  // beyond that its chunks hold a few elements per (tau, R) row, short scattered accesses, and
+  // the two coalesced passes are the faster route.
+  const bool fused_pref = c->N_R <= kPF || !two_pass_ok;
+  if (fused_pref && mfma_ok(c->n_tau, n_omega) && drain_dispatch(c, T, n_omega, parity, in, out, n2, s))
     return check_launch("drain");
-  // two passes through `out`: needs room for n_tau rows there
-  if ((const void*)in != (const void*)out && n_omega < c->n_tau)
+  if (!two_pass_ok)
     return fail(GW_ERR_UNSUPPORTED, "this mesh / grid needs n_omega >= n_tau or an in-place drain");
   gw_status st = launch_fourier(c, in, sizeof(TI) == 16 ? GW_C128 : GW_C64, out, ot, n, -1, s);
   if (st != GW_OK) return st;

@@ -333,6 +333,26 @@ gw_status gw_update_mu(const gw_cell* cell, const void* Hk, const void* Sigma, c
                        void* G, void* work, size_t work_size, double* n_dev, double* mu_out, double* n_out,
                        void* stream);
 
+/* Imaginary time from Matsubara frequency for the Green's function (the way back that closes the
+ * Eqs. (1)-(4) cycle, Sec. 2): G(k, tau_i) on the cell's tau grid from G(k, i w_m) at the first
+ * n_omega fermionic frequencies w_m = (2 m + 1) pi / beta,
+ *   G(tau) = (1 / beta) sum over every fermionic w_n of exp(-i w_n tau) G(i w_n),
+ * with the negative frequencies taken as G(k, -i w) = G(k, i w)^H (Hermitian H, Sigma_x and
+ * Sigma(k, -i w) = Sigma(k, i w)^H) and the high-frequency tails I / (i w) + c2 / (i w)^2,
+ * c2 = H(k) - mu + Sigma_x(k), summed in closed form (-I/2 and c2 (2 tau - beta) / 4):
+ *   G(tau) = -I/2 + c2 (2 tau - beta) / 4
+ *            + (1 / beta) sum_{m < n_omega} [e^{-i w_m tau} R_m + e^{+i w_m tau} R_m^H],
+ *   R_m = G(i w_m) - I / (i w_m) - c2 / (i w_m)^2.
+ * At tau = beta^- this gives exactly the count of gw_density_omega (-g / N_k sum_k Tr G(k, beta^-)).
+ *   G:       DEVICE complex128 [n_omega][N_k][N_orb][N_orb] (gw_green_dyson's output at mu), n_omega <= 512;
+ *   Hk:      DEVICE complex128 [N_k][N_orb][N_orb];  Sigma_x: same shape or NULL;
+ *   mix:     in (0, 1]: G_tau <- mix G(tau) + (1 - mix) G_tau, the linear mixing of successive
+ *            iterates of the self-consistent loop (G_tau is not read when mix = 1);
+ *   G_tau:   DEVICE complex128 [n_tau][N_k][N_orb][N_orb], not overlapping the inputs.
+ * FP64 arithmetic; enqueued on `stream`. */
+gw_status gw_green_tau(const gw_cell* cell, const void* G, int n_omega, const void* Hk, const void* Sigma_x, double mu,
+                       double mix, void* G_tau, void* stream);
+
 /* Host helper: the inverse of gw_tau2omega_matrix(n_tau, tau, n_omega, omega) (needs
  * n_omega == n_tau), FP64 Gauss-Jordan with partial pivoting.  With it, gw_tau2omega (parity
  * 0, n_omega = n_tau) takes frequency samples back to the tau samples of the piecewise-linear

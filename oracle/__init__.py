@@ -19,7 +19,9 @@ It computes, slowly and by the plain definitions of Kutepov's paper:
 * the screened interaction W~ = W - V from Eq. (2), and the inverse of the tau -> Matsubara
   matrix;
 * the static (exchange) self-energy: Eq. (8) with W~ -> V and G(tau) -> -G(beta);
-* the Dyson equation for G, Eq. (4);
+* the Dyson equation for G, Eq. (4), and the way back from Matsubara frequency to imaginary time
+  for G with its high-frequency tails in closed form;
+* one cycle of the self-consistent loop (Eqs. (1)-(4)) chained from the functions above;
 * the interstitial-grid blocks of P and Sigma, Eqs. (6), (7), (9), (10).
 
 Conventions (the paper leaves them open; the readings are the same as the
@@ -47,5 +49,6 @@ from . import bruteforce  # noqa: F401
 from .cutoff import plan_pairs, polarizability_r_block_cut, self_energy_r_block_cut  # noqa: F401
 from .dyson import screened_interaction, omega_to_tau_matrix  # noqa: F401
 from .exchange import exchange_r, exchange_k  # noqa: F401
-from .green import green_dyson  # noqa: F401
+from .green import green_dyson, green_tau  # noqa: F401
+from . import scgw  # noqa: F401
 from .interstitial import polarizability_int, self_energy_int  # noqa: F401

@@ -59,6 +59,7 @@ SIGNATURES = {
     "gw_update_mu": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_double, _c_double, _c_double, _c_double, _c_double,
                               _c_int, _vp, _vp, ctypes.c_size_t, _vp, _dp, _dp, _vp]),
     "gw_omega2tau_matrix": (_c_int, [_c_int, _dp, _c_int, _dp, _dp]),
+    "gw_green_tau": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _c_double, _c_double, _vp, _vp]),
     "gw_status_string": (ctypes.c_char_p, [_c_int]),
     "gw_last_error": (ctypes.c_char_p, []),
 }
@@ -477,6 +478,22 @@ def gw_update_mu(cell, Hk, G, work, n_dev, spin_factor, n_target, mu_lo, mu_hi, 
                             work.numel() * work.element_size(), _ptr(n_dev, 1, "n_dev"), ctypes.byref(mu),
                             ctypes.byref(n), _stream()), "gw_update_mu")
     return mu.value, n.value
+
+
+def gw_green_tau(cell, G, Hk, mu, G_tau, Sigma_x=None, mix=1.0):
+    """G(k, tau) on the cell's grid from G(k, i w_m) (complex128 [n_omega][N_k][N_orb][N_orb]) by the
+    Matsubara sum with the 1 / (i w) and 1 / (i w)^2 tails in closed form; G_tau: complex128
+    [n_tau][N_k][N_orb][N_orb], set to mix G(tau) + (1 - mix) G_tau."""
+    torch = _torch()
+    per = cell.N_R * cell.N_orb * cell.N_orb
+    if G.numel() % per or G.numel() == 0:
+        raise ValueError("G must hold n_omega * N_k * N_orb^2 elements")
+    for t, name in ((G, "G"), (Hk, "Hk"), (G_tau, "G_tau"), (Sigma_x, "Sigma_x")):
+        if t is not None and t.dtype != torch.complex128:
+            raise TypeError(f"{name} must be complex128")
+    _check(lib.gw_green_tau(cell.handle, _ptr(G, G.numel(), "G"), G.numel() // per, _ptr(Hk, per, "Hk"),
+                            None if Sigma_x is None else _ptr(Sigma_x, per, "Sigma_x"), float(mu), float(mix),
+                            _ptr(G_tau, cell.n_tau * per, "G_tau"), _stream()), "gw_green_tau")
 
 
 def gw_omega2tau_matrix(tau, omega):

@@ -194,6 +194,7 @@ gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom,
   if (st == GW_OK) st = upload(c, &c->orb_off_dev, c->orb_off.data(), c->orb_off.size());
   if (st == GW_OK) st = upload(c, &c->pb_off_dev, c->pb_off.data(), c->pb_off.size());
   if (st == GW_OK) st = upload(c, &c->species_dev, c->species.data(), c->species.size());
+  if (st == GW_OK) st = upload(c, &c->tau_dev, c->tau.data(), c->tau.size());
   if (st != GW_OK) {
     std::string msg = g_last_error;
     gw_cell_destroy(c);

@@ -167,6 +167,81 @@ __global__ __launch_bounds__(256) void dy_count(const double2* __restrict__ G, c
   if (threadIdx.x == 0) *n_dev = g / n_k * (0.5 * (double)n_k * n + 2.0 / beta * part[0]);
 }
 
+// G(k, tau) from G(k, i w_m) at the first n_om fermionic frequencies w_m = (2 m + 1) pi / beta:
+//   G(tau) = (1 / beta) sum over all n of exp(-i w_n tau) G(i w_n), the negative frequencies
+//   taken as G(-i w) = G(i w)^H, and the tails 1 / (i w), c2 / (i w)^2 of G, c2 = H - mu + Sigma_x,
+//   summed in closed form (their transforms on 0 < tau < beta are -1/2 and (2 tau - beta) / 4):
+//   G(tau) = -I / 2 + c2 (2 tau - beta) / 4
+//            + (1 / beta) sum_{m < n_om} [exp(-i w_m tau) R_m + exp(+i w_m tau) R_m^H],
+//   R_m = G(i w_m) - I / (i w_m) - c2 / (i w_m)^2 = G(i w_m) + i I / w_m + c2 / w_m^2.
+// A workgroup takes 256 matrix elements (k, a, b) and a chunk of 16 time points; the phases
+// of the chunk are tabulated in LDS first.
+constexpr int kGT = 16;  // time points per chunk
+__global__ __launch_bounds__(256) void dy_green_tau(const double2* __restrict__ G, const double2* __restrict__ H,
+                                                    const double2* __restrict__ Sx, double mu, int n_om, int n_k,
+                                                    int n, double beta, const double* __restrict__ tau, int n_tau,
+                                                    double mix, double2* __restrict__ out) {
+  extern __shared__ double2 ph[];  // [kGT][n_om]: exp(-i w_m tau_i) / beta
+  const int i0 = blockIdx.y * kGT, nt = n_tau - i0 < kGT ? n_tau - i0 : kGT;
+  for (int e = threadIdx.x; e < nt * n_om; e += 256) {
+    const int i = e / n_om, m = e - i * n_om;
+    double sn, cs;
+    sincospi((2.0 * m + 1.0) * (tau[i0 + i] / beta), &sn, &cs);
+    ph[e] = make_double2(cs / beta, -sn / beta);
+  }
+  __syncthreads();
+  const long long nn = (long long)n * n, total = (long long)n_k * nn;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long long k = e / nn;
+  const int a = (int)((e - k * nn) / n), b = (int)(e - k * nn - (long long)a * n);
+  const long long eab = e, eba = k * nn + (long long)b * n + a;
+  // c2 of (a, b) and of (b, a)
+  double2 c2 = H[eab], c2t = H[eba];
+  if (Sx) {
+    const double2 x = Sx[eab], y = Sx[eba];
+    c2.x += x.x;
+    c2.y += x.y;
+    c2t.x += y.x;
+    c2t.y += y.y;
+  }
+  if (a == b) {
+    c2.x -= mu;
+    c2t.x -= mu;
+  }
+  double accr[kGT], acci[kGT];
+#pragma unroll
+  for (int i = 0; i < kGT; ++i) {
+    const double t = i < nt ? tau[i0 + i] : 0.0;
+    accr[i] = (a == b ? -0.5 : 0.0) + c2.x * (2.0 * t - beta) * 0.25;
+    acci[i] = c2.y * (2.0 * t - beta) * 0.25;
+  }
+  for (int m = 0; m < n_om; ++m) {
+    const double w = (2.0 * m + 1.0) * M_PI / beta, iw2 = 1.0 / (w * w);
+    const double2 g = G[(long long)m * total + eab], gt = G[(long long)m * total + eba];
+    // R_m(a, b) and conj(R_m(b, a))
+    double rr = g.x + c2.x * iw2, ri = g.y + c2.y * iw2 + (a == b ? 1.0 / w : 0.0);
+    double hr = gt.x + c2t.x * iw2, hi = -(gt.y + c2t.y * iw2 + (a == b ? 1.0 / w : 0.0));
+#pragma unroll
+    for (int i = 0; i < kGT; ++i) {
+      const double2 p = ph[i * n_om + m];  // exp(-i w tau) / beta; its conjugate for the R^H term
+      accr[i] += p.x * rr - p.y * ri + p.x * hr + p.y * hi;
+      acci[i] += p.x * ri + p.y * rr + p.x * hi - p.y * hr;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kGT; ++i)
+    if (i < nt) {
+      double2* o = out + (long long)(i0 + i) * total + eab;
+      if (mix == 1.0) {
+        *o = make_double2(accr[i], acci[i]);
+      } else {
+        const double2 old = *o;
+        *o = make_double2(mix * accr[i] + (1.0 - mix) * old.x, mix * acci[i] + (1.0 - mix) * old.y);
+      }
+    }
+}
+
 template <class MT> struct Cx;
 template <> struct Cx<double2> {
   typedef double R;
@@ -710,6 +785,30 @@ gw_status gw_update_mu(const gw_cell* c, const void* Hk, const void* Sigma, cons
   *mu_out = x;
   *n_out = fx + n_target;
   return GW_OK;
+}
+
+gw_status gw_green_tau(const gw_cell* c, const void* G, int n_omega, const void* Hk, const void* Sigma_x, double mu,
+                       double mix, void* G_tau, void* stream) {
+  if (!c) return fail(GW_ERR_ARG, "cell is NULL");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(GW_ERR_HIP, "hipGetDevice failed");
+  if (cur != c->device) return fail(GW_ERR_ARG, "current device differs from the cell's device");
+  if (!G || !Hk || !G_tau) return fail(GW_ERR_ARG, "NULL pointer");
+  if (n_omega < 1 || n_omega > 512) return fail(GW_ERR_SHAPE, "n_omega must be in [1, 512]");
+  if (!std::isfinite(mu)) return fail(GW_ERR_ARG, "mu must be finite");
+  if (!(mix > 0.0 && mix <= 1.0)) return fail(GW_ERR_ARG, "mix must be in (0, 1]");
+  const long long total = (long long)c->N_R * c->N_orb * c->N_orb;
+  const size_t ng = (size_t)n_omega * total * 16, no = (size_t)c->n_tau * total * 16, nh = (size_t)total * 16;
+  if (!disjoint(G_tau, no, G, ng) || !disjoint(G_tau, no, Hk, nh) || (Sigma_x && !disjoint(G_tau, no, Sigma_x, nh)))
+    return fail(GW_ERR_ARG, "G_tau overlaps an input");
+  const dim3 grid((unsigned)((total + 255) / 256), (unsigned)((c->n_tau + kGT - 1) / kGT));
+  const size_t lds = (size_t)kGT * n_omega * sizeof(double2);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)dy_green_tau, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(dy_green_tau, grid, dim3(256), lds, (hipStream_t)stream, (const double2*)G,
+                     (const double2*)Hk, (const double2*)Sigma_x, mu, n_omega, c->N_R, c->N_orb, c->beta,
+                     c->tau_dev, c->n_tau, mix, (double2*)G_tau);
+  return check_launch("gw_green_tau");
 }
 
 gw_status gw_omega2tau_matrix(int n_tau, const double* tau, int n_omega, const double* omega, double* Ti) {

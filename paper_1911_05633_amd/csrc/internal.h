@@ -53,6 +53,7 @@ struct gw_cell {
   int n_tau = 0;
   double beta = 0;
   std::vector<double> tau;             // host, the grid given at creation
+  double* tau_dev = nullptr;           // the same on the device
   std::vector<int> minusR;             // host
   int* minusR_dev = nullptr;
   int* orb_off_dev = nullptr;

@@ -91,3 +91,64 @@ def test_update_mu_reaches_band_chemical_potential():
     assert abs(n - target) <= 1e-10 and abs(mu - b.mu) < 1e-4
     with pytest.raises(ValueError):
         update_mu(Hk, spec.beta, 64, spec.spin, target, b.mu + 0.5, b.mu + 1.0, 1e-10, 80)
+
+
+def test_tail_transforms_against_brute_force_matsubara_sums():
+    """The closed forms green_tau uses for the two tails: (1/beta) sum over all fermionic n of
+    exp(-i w_n tau) / (i w_n) = -1/2 and of exp(-i w_n tau) / (i w_n)^2 = (2 tau - beta) / 4 on
+    0 < tau < beta, checked by direct symmetric sums; and green_tau returns exactly those forms
+    for a G made of the tails alone, at any number of frequencies."""
+    from oracle.green import green_tau
+    beta = 3.0
+    n = np.arange(-400000, 400000)
+    w = (2 * n + 1) * np.pi / beta
+    for t in (0.3, 1.1, 2.6):
+        s1 = np.sum(np.exp(-1j * w * t) / (1j * w)).real / beta
+        s2 = np.sum(np.exp(-1j * w * t) / (1j * w) ** 2).real / beta
+        assert abs(s1 + 0.5) < 2e-5 and abs(s2 - (2 * t - beta) / 4) < 2e-6
+    rng = np.random.default_rng(4)
+    c2 = rng.standard_normal((2, 3, 3)) + 1j * rng.standard_normal((2, 3, 3))
+    c2 = c2 + np.conj(np.swapaxes(c2, -1, -2))
+    Hk, mu = c2 + 0.4 * np.eye(3)[None], 0.4
+    for n_om in (1, 7):
+        om = fermionic_points(n_om, beta)
+        Gw = np.eye(3)[None, None] / (1j * om[:, None, None, None]) + c2[None] / (1j * om[:, None, None, None]) ** 2
+        taus = np.array([0.0, 0.7, 2.2, beta])
+        Gt = green_tau(Gw, Hk, mu, beta, taus)
+        ex = -0.5 * np.eye(3)[None, None] + c2[None] * ((2 * taus - beta) / 4)[:, None, None, None]
+        assert np.max(np.abs(Gt - ex)) < 1e-13
+
+
+def test_green_tau_converges_to_the_band_green_function():
+    """For the free Dyson solution the sum converges to -U (1 - f) e^{-x tau} U^+ on the whole grid
+    (end points 0+ and beta- included), faster than the third power of the frequency count."""
+    from oracle.green import green_tau
+    spec = cells.tiny(complex_hopping=True, beta=10.0)
+    hop, b, Gk, C = cells.inputs(spec)
+    Hk = sc.hamiltonian_k(spec, hop)
+    err = []
+    for n_om in (50, 200, 800):
+        Gw = green_dyson(Hk, b.mu, fermionic_points(n_om, spec.beta))
+        err.append(np.max(np.abs(green_tau(Gw, Hk, b.mu, spec.beta, sc.tau_grid(spec)) - Gk)))
+    assert err[0] / err[1] > 30 and err[1] / err[2] > 30 and err[2] < 1e-8
+
+
+def test_green_tau_count_at_beta_equals_the_tail_summed_count():
+    """-g / N_k sum_k Tr G(k, beta^-) of the reconstruction is the Matsubara count of density_omega,
+    for a G with a causal self-energy and a static part (an identity of the two formulas)."""
+    from oracle.green import density_omega, green_tau
+    spec = cells.two_species()
+    hop, b, Gk, C = cells.inputs(spec)
+    Hk = sc.hamiltonian_k(spec, hop)
+    rng = np.random.default_rng(8)
+    n, n_om = spec.N_orb, 12
+    X = rng.standard_normal((spec.N_R, n, n)) + 1j * rng.standard_normal((spec.N_R, n, n))
+    om = fermionic_points(n_om, spec.beta)
+    S = 0.2 * (X @ np.conj(np.swapaxes(X, -1, -2)) / n)[None] / (1j * om[:, None, None, None] - 0.3)
+    Y = rng.standard_normal((spec.N_R, n, n))
+    Sx = (0.1 * (Y + np.swapaxes(Y, -1, -2))).astype(np.complex128)
+    mu = b.mu + 0.1
+    Gw = green_dyson(Hk, mu, om, Sigma=S, Sigma_x=Sx)
+    Gt = green_tau(Gw, Hk, mu, spec.beta, [spec.beta], Sigma_x=Sx)
+    n_tau = -spec.spin / spec.N_R * np.einsum("kaa->", Gt[0]).real
+    assert abs(n_tau - density_omega(Gw, Hk, mu, spec.beta, spec.spin, Sx)) < 1e-11 * n_tau

@@ -400,6 +400,23 @@ def pairs_bench(args, torch, log):
             return e0.elapsed_time(e1) / reps
 
         ms_cut, ms_dense = timed(cut), timed(dense)
+        # packed storage: P and W hold the kept blocks only
+        per_tau = cell.packed_elems()
+        cdt = torch.complex128 if prec == "fp64" else torch.complex64
+        Ppk = torch.empty((spec.n_tau, per_tau), dtype=cdt, device="cuda")
+        Wpk = torch.empty_like(Ppk)
+        g.gw_polarizability_packed(cell, d["GR"], Wpk, spec.spin, prec=prec)  # any finite W will do
+
+        def packed():
+            g.gw_polarizability_packed(cell, d["GR"], Ppk, spec.spin, prec=prec)
+            g.gw_self_energy_packed(cell, d["GR"], Wpk, d["S"], prec=prec)
+
+        def packed_drain():
+            g.gw_drain_packed(cell, d["TP"], Ppk, d["P"], parity=1)
+
+        ms_packed, ms_pdrain = timed(packed), timed(packed_drain)
+        es = Ppk.element_size()
+        del Ppk, Wpk
         plan = cell.pairs()
         kept_elems = float((plan[:, 3].astype(np.int64) * plan[:, 4]).sum())   # sum over kept blocks of mA mB
         dense_elems = float(spec.N_R) * spec.N_pb ** 2
@@ -407,7 +424,10 @@ def pairs_bench(args, torch, log):
                "dense_blocks": spec.N_R * spec.n_atoms ** 2, "ms_cutoff": ms_cut, "ms_dense": ms_dense,
                "us_per_kept_block_and_tau": ms_cut * 1e3 / (nk * spec.n_tau),
                "P_elements_per_tau_kept": kept_elems, "P_elements_per_tau_dense": dense_elems,
-               "storage_ratio_dense_over_kept": dense_elems / kept_elems}
+               "storage_ratio_dense_over_kept": dense_elems / kept_elems,
+               "ms_packed": ms_packed, "ms_packed_drain_to_dense_k": ms_pdrain,
+               "packed_P_bytes": float(spec.n_tau * per_tau * es),
+               "dense_P_bytes": float(spec.n_tau * dense_elems * es)}
         log(f"cutoff {kind}: {row}")
         rows.append(row)
         del d, cell
@@ -415,7 +435,8 @@ def pairs_bench(args, torch, log):
     a = np.array([r["atoms"] for r in rows], dtype=float)
     t = np.array([r["ms_cutoff"] for r in rows])
     slope = float(np.polyfit(np.log(a), np.log(t), 1)[0])
-    out = {"metric": "cutoff path: P+Sigma ms vs cell size at fixed r_c (kernels walking the kept-block list)",
+    out = {"metric": "cutoff path: P+Sigma ms vs cell size at fixed r_c (kernels walking the kept-block list; "
+                     "dense and packed storage of P and W)",
            "unit": "ms", "n_gpus": 1, "dtype": prec, "data": "synthetic",
            "config": {"workload": "Si cells of 8, 24, 40, 72 atoms, n_tau 48, r_b 2.5 A, r_c 4.6 A, "
                                   "m_B 60, m_C 16", "prec": prec},

@@ -207,6 +207,45 @@ gw_status gw_polarizability_pairs(const gw_cell* cell, const void* GR, void* P, 
 gw_status gw_self_energy_pairs(const gw_cell* cell, const void* GR, const void* WR, void* Sigma,
                                gw_precision prec, void* stream);
 
+/* Packed storage of the kept blocks (Sec. 2: two-point functions stored only for the pairs
+ * within R_max, each in the product basis of its distance tier).  A tau slice of a packed tensor
+ * holds the kept (R, A, B) blocks of gw_cell_pairs one after the other, in that order, each as
+ * its mA x mB kept functions row-major; *per_tau = sum over the kept blocks of mA mB (elements
+ * per tau slice).  GW_ERR_ARG without a list. */
+gw_status gw_cell_packed_size(const gw_cell* cell, long long* per_tau);
+
+/* Eq. (5) over the kept blocks, written in the packed layout: P [n_tau][per_tau], the block
+ * (R, A, B) holding P^R_IJ(tau) for I < mA, J < mB (the values gw_polarizability_pairs writes
+ * there).  complex128 for GW_FP64, complex64 otherwise (GW_BF16X3 runs the FP32 matrix cores here).
+ * GR as for gw_polarizability.  GW_ERR_ARG without a list or for overlapping tensors. */
+gw_status gw_polarizability_packed(const gw_cell* cell, const void* GR, void* P, double spin_factor,
+                                   gw_precision prec, void* stream);
+
+/* Eq. (8) over the kept blocks with W^R(tau) read in the packed layout (W_IJ taken as zero beyond
+ * a block's mA x mB functions, as in gw_self_energy_pairs); Sigma dense complex128
+ * [n_tau][N_R][N_orb][N_orb], written on the kept blocks only.  Storage types as
+ * gw_polarizability_packed. */
+gw_status gw_self_energy_packed(const gw_cell* cell, const void* GR, const void* WR, void* Sigma,
+                                gw_precision prec, void* stream);
+
+/* R -> k of a packed tensor: out[t][q][pA + I][pB + J] = sum over the kept blocks (R, A, B) of
+ * exp(-i q.R) F_(R,A,B)(t)[I][J], dense complex [n_tau][N_k][N_pb][N_pb] (every element written:
+ * zero where no kept block has the function pair).  in: packed [n_tau][per_tau].  FP64
+ * arithmetic; in and out must not overlap. */
+gw_status gw_fourier_r2k_packed(const gw_cell* cell, const void* in, gw_dtype in_type, void* out,
+                                gw_dtype out_type, void* stream);
+
+/* k -> R into the packed layout: F_(R,A,B)(t)[I][J] = N_k^-1 sum_q exp(+i q.R) in[t][q][pA + I][pB + J]
+ * for the kept blocks only.  in: dense [n_tau][N_k][N_pb][N_pb]; out: packed.  FP64 arithmetic. */
+gw_status gw_fourier_k2r_packed(const gw_cell* cell, const void* in, gw_dtype in_type, void* out,
+                                gw_dtype out_type, void* stream);
+
+/* gw_fourier_r2k_packed into out, then gw_tau2omega in place on out (same T, n_omega and parity
+ * rules): out[m][q][...] = sum_tau T[m][tau] (R -> k of the packed tensor)(tau).  out must hold
+ * max(n_tau, n_omega) N_k N_pb^2 elements. */
+gw_status gw_drain_packed(const gw_cell* cell, const void* T, int n_omega, int parity, const void* in,
+                          gw_dtype in_type, void* out, gw_dtype out_type, void* stream);
+
 /* Host helper: the FP64 matrix T[n_omega][n_tau] (complex, interleaved) that integrates
  * the piecewise-linear interpolant of F(tau) against exp(i omega_m tau) over [0, beta]
  * exactly (trapezoid rule at omega = 0).  tau: host, increasing; omega: host.

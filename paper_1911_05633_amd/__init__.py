@@ -45,6 +45,12 @@ SIGNATURES = {
     "gw_cell_set_pairs": (_c_int, [_vp, _dp, _dp, _c_double, _c_double, _ip]),
     "gw_cell_pairs": (_c_int, [_vp, ctypes.POINTER(ctypes.c_longlong), _ip, ctypes.c_longlong]),
     "gw_polarizability_pairs": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
+    "gw_cell_packed_size": (_c_int, [_vp, ctypes.POINTER(ctypes.c_longlong)]),
+    "gw_polarizability_packed": (_c_int, [_vp, _vp, _vp, _c_double, _c_int, _vp]),
+    "gw_self_energy_packed": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
+    "gw_fourier_r2k_packed": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp]),
+    "gw_fourier_k2r_packed": (_c_int, [_vp, _vp, _c_int, _vp, _c_int, _vp]),
+    "gw_drain_packed": (_c_int, [_vp, _vp, _c_int, _c_int, _vp, _c_int, _vp, _c_int, _vp]),
     "gw_self_energy_pairs": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
     "gw_polarizability_int": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _c_double, _c_int, _vp]),
     "gw_self_energy_int": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _c_int, _vp]),
@@ -189,6 +195,12 @@ class Cell:
                                      float(r_c), mt.ctypes.data_as(_ip)), "gw_cell_set_pairs")
         return len(self.pairs())
 
+    def packed_elems(self):
+        """Elements per tau slice of the packed layout of the kept blocks."""
+        n = ctypes.c_longlong()
+        _check(lib.gw_cell_packed_size(self.handle, ctypes.byref(n)), "gw_cell_packed_size")
+        return n.value
+
     def pairs(self):
         """The planned blocks as an int array [n][5] = (R, A, B, mA, mB)."""
         n = ctypes.c_longlong()
@@ -265,6 +277,54 @@ def gw_self_energy_pairs(cell, GR, WR, Sigma, prec=None):
         raise TypeError("Sigma is always complex128")
     _check(lib.gw_self_energy_pairs(cell.handle, _ptr(GR, cell.elems(0), "GR"), _ptr(WR, cell.elems(1), "WR"),
                                     _ptr(Sigma, cell.elems(0), "Sigma"), p, _stream()), "gw_self_energy_pairs")
+
+
+def gw_polarizability_packed(cell, GR, P, spin_factor=2.0, prec=None):
+    """Eq. (5) over the kept blocks, P in the packed layout [n_tau][cell.packed_elems()]."""
+    p = _prec(prec, GR)
+    want = GW_C128 if p == GW_FP64 else GW_C64
+    if _dtype_code(GR) != want or _dtype_code(P) != want:
+        raise TypeError("GR and P must be complex128 for fp64 and complex64 otherwise")
+    _check(lib.gw_polarizability_packed(cell.handle, _ptr(GR, cell.elems(0), "GR"),
+                                        _ptr(P, cell.n_tau * cell.packed_elems(), "P"), float(spin_factor), p,
+                                        _stream()), "gw_polarizability_packed")
+
+
+def gw_self_energy_packed(cell, GR, WR, Sigma, prec=None):
+    """Eq. (8) over the kept blocks with W in the packed layout; Sigma dense complex128."""
+    p = _prec(prec, GR)
+    want = GW_C128 if p == GW_FP64 else GW_C64
+    if _dtype_code(GR) != want or _dtype_code(WR) != want:
+        raise TypeError("GR and WR must be complex128 for fp64 and complex64 otherwise")
+    if _dtype_code(Sigma) != GW_C128:
+        raise TypeError("Sigma is always complex128")
+    _check(lib.gw_self_energy_packed(cell.handle, _ptr(GR, cell.elems(0), "GR"),
+                                     _ptr(WR, cell.n_tau * cell.packed_elems(), "WR"),
+                                     _ptr(Sigma, cell.elems(0), "Sigma"), p, _stream()), "gw_self_energy_packed")
+
+
+def gw_fourier_r2k_packed(cell, inp, out):
+    """R -> k of a packed tensor into the dense k-space layout [n_tau][N_k][N_pb][N_pb]."""
+    _check(lib.gw_fourier_r2k_packed(cell.handle, _ptr(inp, cell.n_tau * cell.packed_elems(), "in"),
+                                     _dtype_code(inp), _ptr(out, cell.elems(1), "out"), _dtype_code(out),
+                                     _stream()), "gw_fourier_r2k_packed")
+
+
+def gw_fourier_k2r_packed(cell, inp, out):
+    """k -> R of a dense k-space tensor into the packed layout (kept blocks only)."""
+    _check(lib.gw_fourier_k2r_packed(cell.handle, _ptr(inp, cell.elems(1), "in"), _dtype_code(inp),
+                                     _ptr(out, cell.n_tau * cell.packed_elems(), "out"), _dtype_code(out),
+                                     _stream()), "gw_fourier_k2r_packed")
+
+
+def gw_drain_packed(cell, T, inp, out, parity=0):
+    """R -> k of a packed tensor, then tau -> Matsubara in place on out (max(n_tau, n_omega) rows)."""
+    tp, n_omega = _T_ptr(cell, T)
+    rows = max(cell.n_tau, n_omega)
+    _check(lib.gw_drain_packed(cell.handle, tp, n_omega, int(parity),
+                               _ptr(inp, cell.n_tau * cell.packed_elems(), "in"), _dtype_code(inp),
+                               _ptr(out, cell.elems(1, rows), "out"), _dtype_code(out), _stream()),
+           "gw_drain_packed")
 
 
 def _T_ptr(cell, T):

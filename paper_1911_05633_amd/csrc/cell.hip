@@ -195,6 +195,20 @@ gw_status gw_cell_create(gw_cell** out, int n_atoms, const int* species_of_atom,
   if (st == GW_OK) st = upload(c, &c->pb_off_dev, c->pb_off.data(), c->pb_off.size());
   if (st == GW_OK) st = upload(c, &c->species_dev, c->species.data(), c->species.size());
   if (st == GW_OK) st = upload(c, &c->tau_dev, c->tau.data(), c->tau.size());
+  if (st == GW_OK) {
+    // exp(+i k.R) for every (k, R) of the mesh, k.R = 2 pi sum_i j_i n_i / N_i taken modulo one turn
+    std::vector<double2> ph((size_t)NR * NR);
+    for (int kq = 0; kq < NR; ++kq)
+      for (int r = 0; r < NR; ++r) {
+        const int j[3] = {kq / (mesh[1] * mesh[2]), (kq / mesh[2]) % mesh[1], kq % mesh[2]};
+        const int n[3] = {r / (mesh[1] * mesh[2]), (r / mesh[2]) % mesh[1], r % mesh[2]};
+        double frac = 0;
+        for (int i = 0; i < 3; ++i) frac += (double)((j[i] * n[i]) % mesh[i]) / mesh[i];
+        frac -= std::floor(frac);
+        ph[(size_t)kq * NR + r] = make_double2(std::cos(2.0 * M_PI * frac), std::sin(2.0 * M_PI * frac));
+      }
+    st = upload(c, &c->kr_phase_dev, ph.data(), ph.size());
+  }
   if (st != GW_OK) {
     std::string msg = g_last_error;
     gw_cell_destroy(c);

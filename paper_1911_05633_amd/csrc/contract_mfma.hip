@@ -115,6 +115,7 @@ struct PairArgs {
   // list[2 i + 1] = (first product function of B, first orbital of B, 0, 0)
   const int4* list;
   int nlist;
+  long long ptot;  // packed layout: elements per tau slice (sum of mA mB over the kept blocks)
 };
 
 // Block walk shared by the kernels below.  Dense: every (tau, R, iA, iB) in counting order
@@ -1341,6 +1342,74 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // The tau mirror and the two stores are those of p_mfma; the direct block goes through a
 // per-wavefront LDS tile so that its rows leave as contiguous runs.
 // ---------------------------------------------------------------------------
+// Block walk of the general kernels: dense (every (tau, R, iA, iB), B fastest) or, with PACK,
+// (tau, kept block of the cutoff list) with the block's packed offsets: list entry i is
+// (R, mA | mB << 16, first product function of A, first orbital of A),
+// (first product function of B, first orbital of B, packed offset of (R, A, B), packed offset
+// of its mirror (-R, B, A)) -- offsets within one tau slice of the packed layout, where a kept
+// block is stored as its mA x mB functions, row-major.
+struct GBlk {
+  int t, R, iA, iB;
+  int2 oa, ob;
+  int mt, od, om;
+};
+
+template <bool PACK>
+__device__ __forceinline__ void gblk_start(GBlk& k, long long b, const PairArgs& q) {
+  if constexpr (PACK) {
+    k.t = (int)(b / q.nlist);
+    k.iA = (int)(b - (long long)k.t * q.nlist);
+    k.iB = 0;
+    k.R = 0;
+  } else {
+    k.iB = (int)(b % q.cntB);
+    b /= q.cntB;
+    k.iA = (int)(b % q.cntA);
+    b /= q.cntA;
+    k.R = (int)(b % q.NR);
+    k.t = (int)(b / q.NR);
+  }
+}
+
+template <bool PACK>
+__device__ __forceinline__ void gblk_step(GBlk& k, const PairArgs& q) {
+  if constexpr (PACK) {
+    if (++k.iA == q.nlist) {
+      k.iA = 0;
+      ++k.t;
+    }
+  } else {
+    if (++k.iB == q.cntB) {
+      k.iB = 0;
+      if (++k.iA == q.cntA) {
+        k.iA = 0;
+        if (++k.R == q.NR) {
+          k.R = 0;
+          ++k.t;
+        }
+      }
+    }
+  }
+}
+
+template <bool PACK>
+__device__ __forceinline__ void gblk_fill(GBlk& k, const PairArgs& q) {
+  if constexpr (PACK) {
+    const int4 e0 = q.list[2 * k.iA], e1 = q.list[2 * k.iA + 1];
+    k.R = e0.x;
+    k.mt = e0.y;
+    k.oa = make_int2(e0.z, e0.w);
+    k.ob = make_int2(e1.x, e1.y);
+    k.od = e1.z;
+    k.om = e1.w;
+  } else {
+    k.oa = q.offsA[k.iA < q.cntA ? k.iA : 0];
+    k.ob = q.offsB[k.iB < q.cntB ? k.iB : 0];
+    k.mt = q.mA | (q.mB << 16);
+    k.od = k.om = 0;
+  }
+}
+
 constexpr int kGPL = 144;           // padded pair count bound (16 orbitals: 136 pairs)
 constexpr int kGKA = kGPL / 4;      // GEMM1 K steps at most
 constexpr int kGMP = 128;           // padded product-function bound
@@ -1348,7 +1417,7 @@ constexpr int kGJT = kGMP / 16;     // J tiles at most
 constexpr int kGS = 17;             // row stride (elements) of the 16-wide LDS chunks
 constexpr int kGThreads = 512;
 
-template <class RT, class CT>
+template <class RT, class CT, bool PACK = false>
 __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT* __restrict__ P,
                                                   const RT* __restrict__ CpA, const RT* __restrict__ CpB,
                                                   const PairArgs q, double g) {
@@ -1379,7 +1448,7 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
   CT xr, yr;
   const bool xok = tid < q.nA * q.nB;
-  auto fetch = [&](const Blk& k) {
+  auto fetch = [&](const GBlk& k) {
     const int a = tid / q.nB, c = tid - a * q.nB;
     xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
     const int d = tid / q.nA, bb = tid - d * q.nA;
@@ -1396,11 +1465,11 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
   const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
-  Blk cur;
-  blk_start<false>(cur, bbeg < q.nblocks ? bbeg : 0, q);
-  blk_fill<false>(cur, q);
-  Blk nxt = cur;
-  blk_step<false>(nxt, q);
+  GBlk cur;
+  gblk_start<PACK>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  gblk_fill<PACK>(cur, q);
+  GBlk nxt = cur;
+  gblk_step<PACK>(nxt, q);
   __syncthreads();  // pair tables and the minus-R table staged
   if (bbeg < bend) {
     fetch(cur);
@@ -1408,12 +1477,16 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
   }
   __syncthreads();
   for (long long blk = bbeg; blk < bend; ++blk) {
-    const Blk k = cur;
+    const GBlk k = cur;
     const int t = k.t, tm = q.n_tau - 1 - t, mR = mRs[k.R];
     const int pA = k.oa.x, pB = k.ob.x;
+    // functions kept on A and B (all of them when dense): I tiles and J tiles of the block
+    const int kA = k.mt & 0xffff, kB = k.mt >> 16;
+    const bool actk = act && 16 * w < kA;
+    const int nJTk = PACK ? (kB + 15) / 16 : nJT;
     const bool more = blk + 1 < bend;
     if (more) {
-      blk_fill<false>(nxt, q);
+      gblk_fill<PACK>(nxt, q);
       fetch(nxt);
     }
     typename M::acc acc[kGJT][2];
@@ -1448,7 +1521,7 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
         Cb[J * kGS + pc] = CpB[J * q.nppB + 16 * ch + pc];
       }
       __syncthreads();
-      if (act) {
+      if (actk) {
         // GEMM1: A = Q^T (row p' = li, k = p), two chains (Re Q, Im Q)
         typename M::acc d1r = {0, 0, 0, 0}, d1i = {0, 0, 0, 0};
 #pragma unroll
@@ -1468,7 +1541,7 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
         for (int j = 0; j < 4; ++j)
 #pragma unroll
           for (int Jt = 0; Jt < kGJT; ++Jt)
-            if (Jt < nJT) {
+            if (Jt < nJTk) {
               const RT a = Cb[(16 * Jt + li) * kGS + M::drow(lk, j)];
               acc[Jt][0] = M::op(a, d1r[j], acc[Jt][0]);
               acc[Jt][1] = M::op(a, d1i[j], acc[Jt][1]);
@@ -1476,34 +1549,39 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
       }
       __syncthreads();  // Qc and Cb are rewritten by the next chunk
     }
-    // acc[Jt][part][j]: row J = 16 Jt + drow(lk, j), column I = 16 w + li; P_IJ = -g acc
-    if (act) {
-      CT* Pd = P + ((long long)t * q.NR + k.R) * slp;
-      CT* Pm = P + ((long long)tm * q.NR + mR) * slp;
+    // acc[Jt][part][j]: row J = 16 Jt + drow(lk, j), column I = 16 w + li; P_IJ = -g acc.
+    // Dense: P[t][R][pA + I][pB + J] and the mirror P[tm][-R][pB + J][pA + I].  Packed: the
+    // block's kA x kB functions at its offset in slice t, and the mirror block's kB x kA at its
+    // offset in slice tm.
+    if (actk) {
+      CT* Pd = PACK ? P + (long long)t * q.ptot + k.od : P + ((long long)t * q.NR + k.R) * slp;
+      CT* Pm = PACK ? P + (long long)tm * q.ptot + k.om : P + ((long long)tm * q.NR + mR) * slp;
+      const long long sd = PACK ? kB : q.Np, sm = PACK ? kA : q.Np;  // row strides
+      const int cd = PACK ? 0 : pB, rd = PACK ? 0 : pA;               // column / row origins
       const int I = 16 * w + li;
       CR* Tw = Tt + w * 16 * kGS;
 #pragma unroll
       for (int Jt = 0; Jt < kGJT; ++Jt)
-        if (Jt < nJT) {
+        if (Jt < nJTk) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int Jl = M::drow(lk, j), J = 16 * Jt + Jl;
             const double re = -g * (double)acc[Jt][0][j], im = -g * (double)acc[Jt][1][j];
             Tw[li * kGS + Jl] = mk<RT>(re, im);
-            if (t != tm && I < q.mA && J < q.mB) stc(Pm + (long long)(pB + J) * q.Np + pA + I, re, im);
+            if (t != tm && I < kA && J < kB) stc(Pm + (long long)(cd + J) * sm + rd + I, re, im);
           }
           // the wavefront's own tile: lanes 16 r .. 16 r + 15 store row 4 e + r, 16 consecutive J
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int r = 4 * e + lk, J = 16 * Jt + li, Ir = 16 * w + r;
             const CR v = Tw[r * kGS + li];
-            if (Ir < q.mA && J < q.mB) stc(Pd + (long long)(pA + Ir) * q.Np + pB + J, (double)v.x, (double)v.y);
+            if (Ir < kA && J < kB) stc(Pd + (long long)(rd + Ir) * sd + cd + J, (double)v.x, (double)v.y);
           }
         }
     }
     if (more) stage();  // Xs, Ys were last read before the chunk loop's final barrier
     cur = nxt;
-    blk_step<false>(nxt, q);
+    gblk_step<PACK>(nxt, q);
     __syncthreads();
   }
 }
@@ -1519,7 +1597,7 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
 // LDS with row loads.  Wavefront w owns the orbitals a' = w and a' = w + 8 of atom A and keeps
 // one accumulator per a'; the sum over a' and over the wavefronts is taken in FP64.
 // ---------------------------------------------------------------------------
-template <class RT, class CT>
+template <class RT, class CT, bool PACK = false>
 __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, const CT* __restrict__ WR,
                                                   double2* __restrict__ S, const RT* __restrict__ CA,
                                                   const RT* __restrict__ CB, const PairArgs q) {
@@ -1540,13 +1618,18 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
   const long long per_blk = (q.nblocks + gridDim.x - 1) / gridDim.x;
   const long long bbeg = (long long)blockIdx.x * per_blk;
   const long long bend = bbeg + per_blk < q.nblocks ? bbeg + per_blk : q.nblocks;
-  Blk cur;
-  blk_start<false>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  GBlk cur;
+  gblk_start<PACK>(cur, bbeg < q.nblocks ? bbeg : 0, q);
   for (long long blk = bbeg; blk < bend; ++blk) {
-    blk_fill<false>(cur, q);
-    const Blk k = cur;
+    gblk_fill<PACK>(cur, q);
+    const GBlk k = cur;
     const CT* Gt = GR + ((long long)k.t * q.NR + k.R) * sl;
-    const CT* Wt = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)k.oa.x * q.Np + k.ob.x;
+    // W of the block: rows I < kA, columns J < kB (all of them when dense; W is zero outside a
+    // kept block's functions), row stride N_pb dense or kB packed
+    const int kA = k.mt & 0xffff, kB = k.mt >> 16;
+    const CT* Wt = PACK ? WR + (long long)k.t * q.ptot + k.od
+                        : WR + ((long long)k.t * q.NR + k.R) * slp + (long long)k.oa.x * q.Np + k.ob.x;
+    const long long ws = PACK ? kB : q.Np;
     if (tid < 256) {
       const int a = tid >> 4, c = tid & 15;
       CR v = mk<RT>(0.0, 0.0);
@@ -1559,14 +1642,16 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
     typename M::acc sr[2], si[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) sr[u] = si[u] = typename M::acc{0, 0, 0, 0};
-    for (int ch = 0; ch < nCh; ++ch) {
+    // W is zero beyond the block's functions: fewer chunks of J and K steps over I
+    const int nChk = PACK ? (kB + 15) / 16 : nCh, nKIk = PACK ? (kA + 3) / 4 : nKI;
+    for (int ch = 0; ch < nChk; ++ch) {
       const int J0 = 16 * ch;
       // W[I][J0 .. J0 + 15] for every I: 16 consecutive elements of a row per 16 lanes
       for (int i = tid; i < q.mpA * 16; i += kGThreads) {
         const int I = i >> 4, Jl = i & 15;
         CR v = mk<RT>(0.0, 0.0);
-        if (I < mA && J0 + Jl < mB) {
-          const CT x = Wt[(long long)I * q.Np + J0 + Jl];
+        if (I < kA && J0 + Jl < kB) {
+          const CT x = Wt[(long long)I * ws + J0 + Jl];
           v = mk<RT>((double)x.x, (double)x.y);
         }
         Wc[I * kGS + Jl] = v;
@@ -1596,7 +1681,7 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         if (ap < nA) {
           // L^T[J][a] = sum_I W[I][J] C^I_{a a'}: A = W^T (row J = li, k = I), two chains
           typename M::acc lr = {0, 0, 0, 0}, lim = {0, 0, 0, 0};
-          for (int ks = 0; ks < nKI; ++ks) {
+          for (int ks = 0; ks < nKIk; ++ks) {
             const int I = 4 * ks + lk;
             const CR wv = Wc[I * kGS + li];
             const RT c = ca(I, li, ap);
@@ -1640,7 +1725,7 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         S[((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + b] = make_double2(-v.x, -v.y);
       }
     }
-    blk_step<false>(cur, q);
+    gblk_step<PACK>(cur, q);
     __syncthreads();  // Xs and Sred are rewritten by the next block
   }
 }
@@ -1674,6 +1759,7 @@ PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, i
   q.nblocks = (long long)n_half * c->N_R * q.cntA * q.cntB;
   q.list = nullptr;
   q.nlist = 0;
+  q.ptot = 0;
   return q;
 }
 
@@ -1805,6 +1891,43 @@ bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
     hipLaunchKernelGGL((s_mfma32<1, 4, 1, true>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
                        (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   return true;
+}
+
+// The general kernels over the kept blocks of the cutoff list, packed layout (list entries with
+// the packed offsets; ptot elements per tau slice).
+void launch_p_mfma_packed(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                          long long ptot, const void* GR, void* P, double g, gw_precision p, hipStream_t s) {
+  PairArgs q = make_args(c, A, B, (c->n_tau + 1) / 2);
+  q.list = list;
+  q.nlist = n;
+  q.ptot = ptot;
+  q.nblocks = (long long)q.n_half * n;
+  if (q.nblocks == 0) return;
+  const unsigned grid = (unsigned)(q.nblocks < c->n_cu ? q.nblocks : c->n_cu);
+  if (p == GW_FP64)
+    hipLaunchKernelGGL((p_mfma_gen<double, double2, true>), dim3(grid), dim3(kGThreads), 0, s, (const double2*)GR,
+                       (double2*)P, A.Cpair, B.Cpair, q, g);
+  else
+    hipLaunchKernelGGL((p_mfma_gen<float, float2, true>), dim3(grid), dim3(kGThreads), 0, s, (const float2*)GR,
+                       (float2*)P, A.Cpair32, B.Cpair32, q, g);
+}
+
+void launch_s_mfma_packed(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, const int4* list, int n,
+                          long long ptot, const void* GR, const void* WR, void* S, gw_precision p, hipStream_t s) {
+  PairArgs q = make_args(c, A, B, c->n_tau);
+  q.list = list;
+  q.nlist = n;
+  q.ptot = ptot;
+  q.nblocks = (long long)c->n_tau * n;
+  if (q.nblocks == 0) return;
+  const long long cap = (long long)(p == GW_FP64 ? 1 : 2) * c->n_cu;
+  const unsigned grid = (unsigned)(q.nblocks < cap ? q.nblocks : cap);
+  if (p == GW_FP64)
+    hipLaunchKernelGGL((s_mfma_gen<double, double2, true>), dim3(grid), dim3(kGThreads), 0, s, (const double2*)GR,
+                       (const double2*)WR, (double2*)S, A.C, B.C, q);
+  else
+    hipLaunchKernelGGL((s_mfma_gen<float, float2, true>), dim3(grid), dim3(kGThreads), 0, s, (const float2*)GR,
+                       (const float2*)WR, (double2*)S, A.C32, B.C32, q);
 }
 
 // General shapes on the matrix cores (one workgroup of 8 wavefronts per compute unit).

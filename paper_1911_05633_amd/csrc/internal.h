@@ -69,6 +69,14 @@ struct gw_cell {
   std::vector<int4*> pair_dev;
   std::vector<int4*> pair_dev_mfma;    // same blocks as two int4 each (see launch_p_mfma_list)
   std::vector<int> pair_cnt;
+  // packed layout of the kept blocks (gw_*_packed): elements per tau slice; per kept block
+  // (R, mA | mB << 16, pA, pB), (offset, 0, 0, 0); per (A, B) pair (CSR over A * n_atoms + B) the
+  // kept blocks (R, mA | mB << 16, offset, 0)
+  long long packed_per_tau = 0;
+  int4* packed_blocks_dev = nullptr;
+  int4* packed_ab_items_dev = nullptr;
+  int* packed_ab_ptr_dev = nullptr;
+  double2* kr_phase_dev = nullptr;     // [N_k][N_R]: exp(+i k.R)
 };
 
 namespace gwr {

@@ -140,13 +140,46 @@ gw_status gw_cell_set_pairs(gw_cell* c, const double* lattice, const double* pos
               mB = m_tier[2 * sB + 1];
             }
             host.insert(host.end(), {R, A, B, mA, mB});
-            groups[(size_t)sA * c->n_species + sB].push_back(
-                make_int4(R, index_in_species[A], index_in_species[B], mA | (mB << 16)));
-            auto& g2 = groups2[(size_t)sA * c->n_species + sB];
-            g2.push_back(make_int4(R, mA | (mB << 16), c->pb_off[A], c->orb_off[A]));
-            g2.push_back(make_int4(c->pb_off[B], c->orb_off[B], 0, 0));
           }
       }
+  // Packed layout of the kept blocks, in list order: block b at offset off[b] of a tau slice,
+  // its mA x mB functions row-major.  The mirror (-R, B, A) of every kept block is kept.
+  const long long nkept = (long long)host.size() / 5;
+  std::vector<long long> off(nkept + 1, 0);
+  std::vector<int> where((size_t)c->N_R * c->n_atoms * c->n_atoms, -1);
+  for (long long b = 0; b < nkept; ++b) {
+    const int* e = &host[(size_t)5 * b];
+    off[b + 1] = off[b] + (long long)e[3] * e[4];
+    where[((size_t)e[0] * c->n_atoms + e[1]) * c->n_atoms + e[2]] = (int)b;
+  }
+  if (off[nkept] > 0x7fffffffLL) return fail(GW_ERR_SHAPE, "packed slice above 2^31 elements");
+  std::vector<int4> blocks;                       // per kept block: (R, mA | mB << 16, pA, pB), (off, 0, 0, 0)
+  std::vector<int> ab_ptr((size_t)c->n_atoms * c->n_atoms + 1, 0);
+  std::vector<int4> ab_items;                     // per (A, B), its kept blocks: (R, mA | mB << 16, off, 0)
+  for (long long b = 0; b < nkept; ++b) {
+    const int* e = &host[(size_t)5 * b];
+    const int R = e[0], A = e[1], B = e[2], mA = e[3], mB = e[4];
+    const int sA = c->species[A], sB = c->species[B];
+    const int mirror = where[((size_t)c->minusR[R] * c->n_atoms + B) * c->n_atoms + A];
+    if (mirror < 0) return fail(GW_ERR_HIP, "pair list is not closed under (R, A, B) -> (-R, B, A)");
+    groups[(size_t)sA * c->n_species + sB].push_back(
+        make_int4(R, index_in_species[A], index_in_species[B], mA | (mB << 16)));
+    auto& g2 = groups2[(size_t)sA * c->n_species + sB];
+    g2.push_back(make_int4(R, mA | (mB << 16), c->pb_off[A], c->orb_off[A]));
+    g2.push_back(make_int4(c->pb_off[B], c->orb_off[B], (int)off[b], (int)off[mirror]));
+    blocks.push_back(make_int4(R, mA | (mB << 16), c->pb_off[A], c->pb_off[B]));
+    blocks.push_back(make_int4((int)off[b], 0, 0, 0));
+    ++ab_ptr[(size_t)A * c->n_atoms + B + 1];
+  }
+  for (size_t i = 1; i < ab_ptr.size(); ++i) ab_ptr[i] += ab_ptr[i - 1];
+  ab_items.resize(nkept > 0 ? nkept : 0);
+  {
+    std::vector<int> fill(ab_ptr.begin(), ab_ptr.end() - 1);
+    for (long long b = 0; b < nkept; ++b) {
+      const int* e = &host[(size_t)5 * b];
+      ab_items[fill[(size_t)e[1] * c->n_atoms + e[2]]++] = make_int4(e[0], e[3] | (e[4] << 16), (int)off[b], 0);
+    }
+  }
   std::vector<int4*> dev(groups.size(), nullptr), dev2(groups.size(), nullptr);
   std::vector<int> cnt(groups.size(), 0);
   for (size_t g = 0; g < groups.size(); ++g) {
@@ -156,10 +189,19 @@ gw_status gw_cell_set_pairs(gw_cell* c, const double* lattice, const double* pos
     st = upload_owned(c, &dev2[g], groups2[g].data(), groups2[g].size());
     if (st != GW_OK) return st;
   }
+  int4 *blocks_dev = nullptr, *items_dev = nullptr;
+  int* ptr_dev = nullptr;
+  if ((st = upload_owned(c, &blocks_dev, blocks.data(), blocks.size())) != GW_OK) return st;
+  if ((st = upload_owned(c, &items_dev, ab_items.data(), ab_items.size())) != GW_OK) return st;
+  if ((st = upload_owned(c, &ptr_dev, ab_ptr.data(), ab_ptr.size())) != GW_OK) return st;
   c->pair_list.swap(host);
   c->pair_dev.swap(dev);
   c->pair_dev_mfma.swap(dev2);
   c->pair_cnt.swap(cnt);
+  c->packed_per_tau = off[nkept];
+  c->packed_blocks_dev = blocks_dev;
+  c->packed_ab_items_dev = items_dev;
+  c->packed_ab_ptr_dev = ptr_dev;
   c->pairs_set = true;
   return GW_OK;
 }

@@ -1603,6 +1603,8 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
                                                   const RT* __restrict__ CB, const PairArgs q) {
   using M = Mma<RT>;
   typedef typename M::cplx CR;
+  constexpr int kGKI = kGMP / 4;           // K steps over I at most
+  constexpr int kWU = kGMP * 16 / kGThreads;  // W values of a chunk per thread
   __shared__ CR Xs[kMaxOrb * kMaxOrb];     // X[a'][b'], 16 x 16 zero padded
   __shared__ CR Ms[16 * 16 * kGS];         // M[a'][J - 16 c][b] (row stride kGS)
   __shared__ CR Wc[kGMP * kGS];            // W[I][J - 16 c]
@@ -1611,34 +1613,77 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
   const int nA = q.nA, nB = q.nB, mA = q.mA, mB = q.mB;
   const int nKI = q.mpA / 4, nCh = (mB + 15) / 16;
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
-  // L's B operand: lane (k = lk, n = a = li) holds C^I_{a a'} for I = 4 ks + lk, per owned a'
-  auto ca = [&](int I, int a, int ap) -> RT {
-    return (I < mA && a < nA && ap < nA) ? CA[((long long)I * nA + a) * nA + ap] : RT(0);
+  // L's B operand, the same for every block: lane (k = lk, n = a = li) holds C^I_{a a'} for
+  // I = 4 ks + lk and the two orbitals a' = w, w + 8 this wavefront owns.  Kept in registers for
+  // FP32; FP64 reads it from the (cache-resident) table at each use, its registers being full.
+  constexpr bool kRegC = sizeof(RT) == 4;
+  auto ca = [&](int ks, int u) -> RT {
+    const int I = 4 * ks + lk, ap = w + 8 * u;
+    return (ks < nKI && I < mA && li < nA && ap < nA) ? CA[((long long)I * nA + li) * nA + ap] : RT(0);
   };
+  RT cav[2][kRegC ? kGKI : 1];
+  if constexpr (kRegC) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int ks = 0; ks < kGKI; ++ks) cav[u][ks] = ca(ks, u);
+  }
   const long long per_blk = (q.nblocks + gridDim.x - 1) / gridDim.x;
   const long long bbeg = (long long)blockIdx.x * per_blk;
   const long long bend = bbeg + per_blk < q.nblocks ? bbeg + per_blk : q.nblocks;
-  GBlk cur;
-  gblk_start<PACK>(cur, bbeg < q.nblocks ? bbeg : 0, q);
-  for (long long blk = bbeg; blk < bend; ++blk) {
-    gblk_fill<PACK>(cur, q);
-    const GBlk k = cur;
-    const CT* Gt = GR + ((long long)k.t * q.NR + k.R) * sl;
-    // W of the block: rows I < kA, columns J < kB (all of them when dense; W is zero outside a
-    // kept block's functions), row stride N_pb dense or kB packed
-    const int kA = k.mt & 0xffff, kB = k.mt >> 16;
-    const CT* Wt = PACK ? WR + (long long)k.t * q.ptot + k.od
-                        : WR + ((long long)k.t * q.NR + k.R) * slp + (long long)k.oa.x * q.Np + k.ob.x;
-    const long long ws = PACK ? kB : q.Np;
+  // The W chunk (and, with the first chunk, the X tile) that is staged next is loaded into
+  // registers a whole chunk ahead; a block's first chunk is loaded during the previous block's last.
+  CT wreg[kWU], xr;
+  auto wsrc = [&](const GBlk& k, long long& ws) -> const CT* {
+    ws = PACK ? (k.mt >> 16) : q.Np;
+    return PACK ? WR + (long long)k.t * q.ptot + k.od
+                : WR + ((long long)k.t * q.NR + k.R) * slp + (long long)k.oa.x * q.Np + k.ob.x;
+  };
+  auto load_w = [&](const GBlk& k, int ch) {
+    long long ws;
+    const CT* Wt = wsrc(k, ws);
+    const int kA = k.mt & 0xffff, kB = k.mt >> 16, J0 = 16 * ch;
+#pragma unroll
+    for (int u = 0; u < kWU; ++u) {
+      const int i = tid + kGThreads * u, I = i >> 4, Jl = i & 15;
+      wreg[u] = ldraw(Wt + (long long)I * ws + J0 + Jl, WR, I < kA && J0 + Jl < kB);
+    }
+  };
+  auto load_x = [&](const GBlk& k) {
+    const int a = (tid & 255) >> 4, c = tid & 15;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR,
+               tid < 256 && a < nA && c < nB);
+  };
+  auto store_w = [&](const GBlk& k, int ch) {
+    const int kA = k.mt & 0xffff, kB = k.mt >> 16, J0 = 16 * ch;
+#pragma unroll
+    for (int u = 0; u < kWU; ++u) {
+      const int i = tid + kGThreads * u, I = i >> 4, Jl = i & 15;
+      const CT v = keep(wreg[u], I < kA && J0 + Jl < kB);
+      Wc[I * kGS + Jl] = mk<RT>((double)v.x, (double)v.y);
+    }
+  };
+  auto store_x = [&](const GBlk& k) {
     if (tid < 256) {
       const int a = tid >> 4, c = tid & 15;
-      CR v = mk<RT>(0.0, 0.0);
-      if (a < nA && c < nB) {
-        const CT x = Gt[(long long)(k.oa.y + a) * q.No + k.ob.y + c];
-        v = mk<RT>((double)x.x, (double)x.y);
-      }
-      Xs[tid] = v;
+      const CT v = keep(xr, a < nA && c < nB);
+      Xs[tid] = mk<RT>((double)v.x, (double)v.y);
     }
+  };
+  GBlk cur;
+  gblk_start<PACK>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  gblk_fill<PACK>(cur, q);
+  GBlk nxt = cur;
+  gblk_step<PACK>(nxt, q);
+  if (bbeg < bend) {
+    load_w(cur, 0);
+    load_x(cur);
+  }
+  for (long long blk = bbeg; blk < bend; ++blk) {
+    const GBlk k = cur;
+    const bool more = blk + 1 < bend;
+    if (more) gblk_fill<PACK>(nxt, q);
+    const int kA = k.mt & 0xffff, kB = k.mt >> 16;
     typename M::acc sr[2], si[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) sr[u] = si[u] = typename M::acc{0, 0, 0, 0};
@@ -1646,17 +1691,15 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
     const int nChk = PACK ? (kB + 15) / 16 : nCh, nKIk = PACK ? (kA + 3) / 4 : nKI;
     for (int ch = 0; ch < nChk; ++ch) {
       const int J0 = 16 * ch;
-      // W[I][J0 .. J0 + 15] for every I: 16 consecutive elements of a row per 16 lanes
-      for (int i = tid; i < q.mpA * 16; i += kGThreads) {
-        const int I = i >> 4, Jl = i & 15;
-        CR v = mk<RT>(0.0, 0.0);
-        if (I < kA && J0 + Jl < kB) {
-          const CT x = Wt[(long long)I * ws + J0 + Jl];
-          v = mk<RT>((double)x.x, (double)x.y);
-        }
-        Wc[I * kGS + Jl] = v;
-      }
+      store_w(k, ch);
+      if (ch == 0) store_x(k);
       __syncthreads();  // Xs (first chunk) and Wc staged; Ms free
+      if (ch + 1 < nChk) {
+        load_w(k, ch + 1);
+      } else if (more) {
+        load_w(nxt, 0);
+        load_x(nxt);
+      }
       // M[a'][J][b] for J = J0 + 2 w, J0 + 2 w + 1: A = X (row a' = li, k = b'),
       // B = C^J (k = b', n = b = li)
 #pragma unroll
@@ -1681,12 +1724,22 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         if (ap < nA) {
           // L^T[J][a] = sum_I W[I][J] C^I_{a a'}: A = W^T (row J = li, k = I), two chains
           typename M::acc lr = {0, 0, 0, 0}, lim = {0, 0, 0, 0};
-          for (int ks = 0; ks < nKIk; ++ks) {
-            const int I = 4 * ks + lk;
-            const CR wv = Wc[I * kGS + li];
-            const RT c = ca(I, li, ap);
-            lr = M::op(wv.x, c, lr);
-            lim = M::op(wv.y, c, lim);
+          if constexpr (kRegC) {
+#pragma unroll
+            for (int ks = 0; ks < kGKI; ++ks)
+              if (ks < nKIk) {
+                const CR wv = Wc[(4 * ks + lk) * kGS + li];
+                lr = M::op(wv.x, cav[u][ks], lr);
+                lim = M::op(wv.y, cav[u][ks], lim);
+              }
+          } else {
+#pragma unroll 2
+            for (int ks = 0; ks < nKIk; ++ks) {
+              const CR wv = Wc[(4 * ks + lk) * kGS + li];
+              const RT cv = ca(ks, u);
+              lr = M::op(wv.x, cv, lr);
+              lim = M::op(wv.y, cv, lim);
+            }
           }
           // S^T[b][a] += sum_J M[a'][J][b] L^T[J][a]; step j: J = J0 + drow(lk, j)
 #pragma unroll
@@ -1711,9 +1764,9 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
           if (w + 8 * u < nA)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-              double2& s = Sred[li * 16 + M::drow(lk, j)];
-              s.x += (double)sr[u][j];
-              s.y += (double)si[u][j];
+              double2& sv = Sred[li * 16 + M::drow(lk, j)];
+              sv.x += (double)sr[u][j];
+              sv.y += (double)si[u][j];
             }
       }
       __syncthreads();
@@ -1725,7 +1778,8 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         S[((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + b] = make_double2(-v.x, -v.y);
       }
     }
-    gblk_step<PACK>(cur, q);
+    cur = nxt;
+    gblk_step<PACK>(nxt, q);
     __syncthreads();  // Xs and Sred are rewritten by the next block
   }
 }
@@ -1920,7 +1974,7 @@ void launch_s_mfma_packed(const gw_cell* c, const SpeciesDev& A, const SpeciesDe
   q.ptot = ptot;
   q.nblocks = (long long)c->n_tau * n;
   if (q.nblocks == 0) return;
-  const long long cap = (long long)(p == GW_FP64 ? 1 : 2) * c->n_cu;
+  const long long cap = c->n_cu;
   const unsigned grid = (unsigned)(q.nblocks < cap ? q.nblocks : cap);
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_mfma_gen<double, double2, true>), dim3(grid), dim3(kGThreads), 0, s, (const double2*)GR,
@@ -1948,8 +2002,8 @@ void launch_s_mfma_gen(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& 
                        void* S, gw_precision p, hipStream_t s, int nt) {
   const PairArgs q = make_args(c, A, B, nt);
   if (q.nblocks == 0) return;
-  // FP32: two workgroups fit a compute unit (registers and LDS), FP64 one
-  const long long cap = (long long)(p == GW_FP64 ? 1 : 2) * c->n_cu;
+  // one workgroup of 8 wavefronts fills a compute unit's registers
+  const long long cap = c->n_cu;
   const unsigned grid = (unsigned)(q.nblocks < cap ? q.nblocks : cap);
   if (p == GW_FP64)
     hipLaunchKernelGGL((s_mfma_gen<double, double2>), dim3(grid), dim3(kGThreads), 0, s, (const double2*)GR,

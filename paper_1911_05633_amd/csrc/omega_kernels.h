@@ -15,6 +15,8 @@
 // read and written exactly once, so in == out (in-place) is safe.
 #pragma once
 
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "cplx.h"
@@ -24,6 +26,13 @@ namespace gwr {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+// GWR_DRAIN=pingpong keeps the paired complex64 drain on the ping-pong kernel; the tests use it to
+// check the wide-chunk kernel against it on the device.
+inline bool wide_disabled() {
+  const char* v = std::getenv("GWR_DRAIN");
+  return v && std::strcmp(v, "pingpong") == 0;
+}
 
 constexpr int kDrainMaxTau = 96;
 constexpr int kDrainMaxOmega = 96;
@@ -577,6 +586,160 @@ __global__ __launch_bounds__(512, 1) void drain_pp(const double2* __restrict__ T
   }
 }
 
+// Wide-chunk variant of the paired (SYM) drain for complex64 storage.  The ping-pong kernel
+// moves 64 columns (CB = 64 / N_R elements per row of in and out, 64 bytes at N_R = 8) per
+// step, and at that segment size the scattered in-place read and write of 2 x n_tau x N_R rows
+// runs at about 2.5 TB/s; 256-byte row segments run near 3.8 TB/s.  So a workgroup here owns
+// 256 columns (CB = 256 / N_R elements of every row) per chunk.  To fit LDS, the staged y
+// (u / v paired rows after the R -> k butterflies, computed in FP64) is held in complex64,
+// the storage precision of the input and the output; the tau contraction stays FP64 MFMA.
+// One chunk per iteration, all eight wavefronts in both phases:
+//   fill(k)   -- every thread pairs and transforms its units (tau row pair, element) of chunk k
+//                from registers into y;
+//   barrier;
+//   fetch(k+1) -- the loads of the next chunk go out, to land during the products;
+//   matrix(k)  -- wavefront w multiplies the 32 columns 32 w .. 32 w + 31 by A (all m tiles)
+//                and stores its tiles (two 16-element runs of one q row: 256 bytes at N_R = 8);
+//   barrier (y is free again).
+// Shapes: N_R in {2, 4, 8}, n_tau <= 48, n_omega <= 16 MT.
+constexpr int kWideThreads = 512;
+constexpr int kWideCols = 256;
+constexpr int kWideMaxTau = 48;
+
+template <int N1, int N2, int N3, int MT>
+__global__ __launch_bounds__(512, 1) void drain_wide(const double2* __restrict__ T, int n_omega, int n_tau,
+                                                     double sgn, const float2* in, float2* out, long long n2,
+                                                     long long nchunks) {
+  constexpr int NR = N1 * N2 * N3;
+  constexpr int NCP = kWideCols;
+  constexpr int CB = NCP / NR;  // elements per chunk; N_R divides 256
+  static_assert(NR * CB == NCP, "the mesh size must divide 256");
+  constexpr int UPL = ((kWideMaxTau / 2) * CB + kWideThreads - 1) / kWideThreads;  // units per thread
+  extern __shared__ double2 lds[];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int nt8 = (n_tau + 7) & ~7;
+  const int ld_t = nt8 + 1;
+  const int half = (n_tau + 1) / 2;
+  const int rows = (n_tau & 1) ? n_tau + 1 : n_tau;  // rows of y that fill() writes
+  float2* Y = reinterpret_cast<float2*>(lds);         // [nt8][NCP]
+  double* As = reinterpret_cast<double*>(Y + nt8 * NCP);  // [16 MT][ld_t]
+  // K row t of the paired form: Re T[m][t] for t < half, Im T[m][n_tau - 1 - t] for half <= t <
+  // n_tau, Im T[m][half - 1] at t = n_tau for odd n_tau; zero beyond
+  for (int i = tid; i < 16 * MT * ld_t; i += kWideThreads) {
+    const int m = i / ld_t, t = i - m * ld_t;
+    double a = 0.0;
+    if (m < n_omega) {
+      if (t < half) a = T[(long long)m * n_tau + t].x;
+      else if (t < n_tau) a = T[(long long)m * n_tau + (n_tau - 1 - t)].y;
+      else if (t == n_tau && (n_tau & 1)) a = T[(long long)m * n_tau + (half - 1)].y;
+    }
+    As[i] = a;
+  }
+  for (int i = tid; i < (nt8 - rows) * NCP; i += kWideThreads) Y[rows * NCP + i] = make_float2(0.f, 0.f);
+  const long long stride = gridDim.x;
+  const long long first = blockIdx.x;
+  const long long kmax = first < nchunks ? (nchunks - first + stride - 1) / stride : 0;
+  const int ksn = nt8 / 4;
+
+  float2 raw[UPL][2 * NR];
+  auto fetch = [&](long long k) {
+    const long long e0 = (first + k * stride) * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+#pragma unroll
+    for (int v = 0; v < UPL; ++v) {
+      const int u = tid + kWideThreads * v, ut = u / CB, uc = u - ut * CB;
+      const bool live = ut < half && uc < cb;
+      const float2* pa = in + (long long)ut * NR * n2 + e0 + uc;
+      const float2* pb = in + (long long)(n_tau - 1 - ut) * NR * n2 + e0 + uc;
+#pragma unroll
+      for (int R = 0; R < NR; ++R) {
+        raw[v][R] = ldraw(pa + R * n2, in, live);
+        raw[v][NR + R] = ldraw(pb + R * n2, in, live);
+      }
+    }
+  };
+  auto fill = [&](long long k) {
+    const long long e0 = (first + k * stride) * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+#pragma unroll
+    for (int v = 0; v < UPL; ++v) {
+      const int u = tid + kWideThreads * v, ut = u / CB, uc = u - ut * CB;
+      if (ut >= half) continue;
+      const bool live = uc < cb;
+      const bool mid = ut == n_tau - 1 - ut;
+      const int t2 = mid ? n_tau : n_tau - 1 - ut;
+      const double sb = mid ? 0.0 : sgn;  // weight of the mirror row
+      // u = y + s y' to row ut, then v = y - s y' as (-v_i, v_r) to row t2
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double wgt = h == 0 ? sb : -sb;
+        double xr[NR], xi[NR];
+#pragma unroll
+        for (int R = 0; R < NR; ++R) {
+          const float2 a = keep(raw[v][R], live), b = keep(raw[v][NR + R], live);
+          xr[R] = fma(wgt, (double)b.x, (double)a.x);
+          xi[R] = fma(wgt, (double)b.y, (double)a.y);
+        }
+        r2k_regs<N1, N2, N3>(xr, xi);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          if (h == 0)
+            Y[ut * NCP + q * CB + uc] = make_float2((float)xr[q], (float)xi[q]);
+          else
+            Y[t2 * NCP + q * CB + uc] = make_float2((float)-xi[q], (float)xr[q]);
+        }
+      }
+    }
+  };
+  // output column of tile h of this wavefront: q row and element within the chunk
+  int oq[2], oe[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = 32 * w + 16 * h + li;
+    oq[h] = col / CB;
+    oe[h] = col - oq[h] * CB;
+  }
+  // one m tile at a time: its products, then its stores, so that the stores of a chunk spread
+  // over the product phase instead of arriving in one burst at its end
+  auto matrix_store = [&](long long k) {
+    const long long e0 = (first + k * stride) * CB;
+    const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      d4 acc[2][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) acc[h][0] = acc[h][1] = d4{0, 0, 0, 0};
+      for (int ks = 0; ks < ksn; ++ks) {
+        const int t = 4 * ks + lk;
+        const float2 y0 = Y[t * NCP + 32 * w + li], y1 = Y[t * NCP + 32 * w + 16 + li];
+        const double a = As[(16 * i + li) * ld_t + t];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)y0.x, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)y0.y, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)y1.x, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)y1.y, acc[1][1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (oe[h] >= cb) continue;
+        float2* p = out + (long long)oq[h] * n2 + e0 + oe[h];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int m = 16 * i + lk + 4 * j;
+          if (m < n_omega) p[(long long)m * NR * n2] = make_float2((float)acc[h][0][j], (float)acc[h][1][j]);
+        }
+      }
+    }
+  };
+  if (kmax > 0) fetch(0);
+  for (long long k = 0; k < kmax; ++k) {
+    fill(k);
+    __syncthreads();  // y of chunk k complete (and, at k = 0, A and the zero rows)
+    if (k + 1 < kmax) fetch(k + 1);
+    matrix_store(k);
+    __syncthreads();  // every wavefront done reading y
+  }
+}
+
 // Plain FP64 VALU transform for sizes outside the MFMA kernel's range (tau <= 256).
 template <class TI, class TO>
 __global__ __launch_bounds__(256) void tau2omega_valu(const double2* __restrict__ T, int n_omega, int n_tau,
@@ -636,6 +799,30 @@ void run_drain(const double2* T, int n_omega, int n_tau, int parity, const TI* i
   constexpr int NR = N1 * N2 * N3;
   const int MT = (n_omega + 15) / 16;
   const int nt4 = (n_tau + 3) & ~3;
+  // wide-chunk kernel for the paired drain in complex64 storage (the mixed path's P drain)
+  if constexpr (NR >= 2 && NR <= 8 && kWideCols % NR == 0 && std::is_same<TI, float2>::value &&
+                std::is_same<TO, float2>::value) {
+    if (parity != 0 && n_tau <= kWideMaxTau && n_omega <= 48 && !wide_disabled()) {
+      constexpr int CBW = kWideCols / NR;
+      const long long nchunks = (n2 + CBW - 1) / CBW;
+      const int nt8 = (n_tau + 7) & ~7;
+      int dev = 0, n_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+        n_cu = 256;
+      const long long grid = nchunks < n_cu ? nchunks : n_cu;
+      auto go = [&](auto kern, int mt) {
+        const size_t lds = (size_t)nt8 * kWideCols * sizeof(float2) + (size_t)16 * mt * (nt8 + 1) * sizeof(double);
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kWideThreads), lds, s, T, n_omega, n_tau,
+                           parity < 0 ? -1.0 : 1.0, (const float2*)in, (float2*)out, n2, nchunks);
+      };
+      if (MT == 1) go(drain_wide<N1, N2, N3, 1>, 1);
+      else if (MT == 2) go(drain_wide<N1, N2, N3, 2>, 2);
+      else go(drain_wide<N1, N2, N3, 3>, 3);
+      return;
+    }
+  }
   // ping-pong kernel: two 64-column streams; needs whole (tau, element) columns per thread
   if constexpr (NR <= kPF) {
     const bool sym = parity != 0 && kPF / NR >= 2;

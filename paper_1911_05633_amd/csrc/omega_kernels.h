@@ -597,9 +597,10 @@ __global__ __launch_bounds__(512, 1) void drain_pp(const double2* __restrict__ T
 //   fill(k)   -- every thread pairs and transforms its units (tau row pair, element) of chunk k
 //                from registers into y;
 //   barrier;
-//   fetch(k+1) -- the loads of the next chunk go out, to land during the products;
-//   matrix(k)  -- wavefront w multiplies the 32 columns 32 w .. 32 w + 31 by A (all m tiles)
-//                and stores its tiles (two 16-element runs of one q row: 256 bytes at N_R = 8);
+//   matrix(k)  -- wavefront w multiplies the 32 columns 32 w .. 32 w + 31 by A, one m tile at a
+//                time, and stores each tile (two 16-element runs of one q row: 256 bytes at
+//                N_R = 8); the loads of chunk k + 1 go out one unit per m tile, so that loads
+//                and stores spread over the product phase and land before the next fill;
 //   barrier (y is free again).
 // Shapes: N_R in {2, 4, 8}, n_tau <= 48, n_omega <= 16 MT.
 constexpr int kWideThreads = 512;
@@ -642,11 +643,12 @@ __global__ __launch_bounds__(512, 1) void drain_wide(const double2* __restrict__
   const int ksn = nt8 / 4;
 
   float2 raw[UPL][2 * NR];
-  auto fetch = [&](long long k) {
+  auto fetch = [&](long long k, int vsel) {  // the loads of unit vsel of every thread, or all (-1)
     const long long e0 = (first + k * stride) * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
 #pragma unroll
     for (int v = 0; v < UPL; ++v) {
+      if (vsel >= 0 && v != vsel) continue;
       const int u = tid + kWideThreads * v, ut = u / CB, uc = u - ut * CB;
       const bool live = ut < half && uc < cb;
       const float2* pa = in + (long long)ut * NR * n2 + e0 + uc;
@@ -699,13 +701,14 @@ __global__ __launch_bounds__(512, 1) void drain_wide(const double2* __restrict__
     oq[h] = col / CB;
     oe[h] = col - oq[h] * CB;
   }
-  // one m tile at a time: its products, then its stores, so that the stores of a chunk spread
-  // over the product phase instead of arriving in one burst at its end
+  // one m tile at a time: the loads of one unit of the next chunk, the tile's products, then its
+  // stores, so that loads and stores spread over the product phase instead of arriving in bursts
   auto matrix_store = [&](long long k) {
     const long long e0 = (first + k * stride) * CB;
     const int cb = (int)((n2 - e0) < CB ? (n2 - e0) : CB);
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
+      if (i < UPL && k + 1 < kmax) fetch(k + 1, i);
       d4 acc[2][2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) acc[h][0] = acc[h][1] = d4{0, 0, 0, 0};
@@ -730,11 +733,12 @@ __global__ __launch_bounds__(512, 1) void drain_wide(const double2* __restrict__
       }
     }
   };
-  if (kmax > 0) fetch(0);
+  if (kmax > 0) fetch(0, -1);
   for (long long k = 0; k < kmax; ++k) {
     fill(k);
     __syncthreads();  // y of chunk k complete (and, at k = 0, A and the zero rows)
-    if (k + 1 < kmax) fetch(k + 1);
+    if (k + 1 < kmax)
+      for (int v = MT; v < UPL; ++v) fetch(k + 1, v);  // units beyond the m tiles' share
     matrix_store(k);
     __syncthreads();  // every wavefront done reading y
   }

@@ -1302,16 +1302,22 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       int pb[9];
 #pragma unroll
       for (int bp = 0; bp < 9; ++bp) pb[bp] = bp < q.nB ? pair_index(bb, bp, q.nB) : 0;
+      // each row a' summed in FP32 (nine products, two interleaved partial sums each for
+      // re and im), rows accumulated in FP64: the split products carry about 2^-16 relative
+      // error, far above the FP32 rounding of a nine-term row
       for (int ap = a0; ap < a1; ++ap) {
         const float2* Kr = Ks + pair_index(a, ap, q.nA) * kKS;
         const float2* Xr = Xs + ap * q.nB;
+        float pr[2] = {0.f, 0.f}, pi[2] = {0.f, 0.f};
 #pragma unroll
         for (int bp = 0; bp < 9; ++bp)
           if (bp < q.nB) {
             const float2 kv = Kr[pb[bp]], x = Xr[bp];
-            sr += (double)kv.x * x.x - (double)kv.y * x.y;
-            si += (double)kv.x * x.y + (double)kv.y * x.x;
+            pr[bp & 1] = fmaf(kv.x, x.x, fmaf(-kv.y, x.y, pr[bp & 1]));
+            pi[bp & 1] = fmaf(kv.x, x.y, fmaf(kv.y, x.x, pi[bp & 1]));
           }
+        sr += (double)pr[0] + (double)pr[1];
+        si += (double)pi[0] + (double)pi[1];
       }
     }
     sr += __shfl_xor(sr, 1);

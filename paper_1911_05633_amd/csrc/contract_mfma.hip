@@ -1121,10 +1121,10 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // 49..64 product functions on both atoms.
 // ---------------------------------------------------------------------------
 
-template <bool LIST = false>
-__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3(
-    const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
-    const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
+template <bool LIST>
+__device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, const float2* __restrict__ WR,
+                                              double2* __restrict__ S, const float* __restrict__ CpA,
+                                              const float* __restrict__ CpB, const PairArgs q) {
   __shared__ __align__(16) __bf16 Wp[4 * kWBP];           // W planes, then the K block (FP32)
   __shared__ __align__(16) __bf16 Cap[2 * 2 * kPL * kCBS];  // C~_A [hi|lo][step][p][slot]
   __shared__ float2 Xs[81];
@@ -1162,14 +1162,13 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   float2 wreg[kW32PF];
   float2 xr;
   const bool lane_ok = lane < q.mB;
-  auto fetch = [&](const Blk& k) {
+  // rows w + 3 u of W for u in [u0, u1)
+  auto fetch = [&](const Blk& k, int u0, int u1) {
     const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(k.oa.x + w) * q.Np + k.ob.x + lane;
     const long long step = 3LL * q.Np;
 #pragma unroll
-    for (int u = 0; u < kW32PF; ++u) {
-      wreg[u] = ldraw(p, WR, lane_ok && w + 3 * u < q.mA);
-      p += step;
-    }
+    for (int u = 0; u < kW32PF; ++u)
+      if (u >= u0 && u < u1) wreg[u] = ldraw(p + u * step, WR, lane_ok && w + 3 * u < q.mA);
   };
   const bool xok = tid < q.nA * q.nB;
   auto fetch_x = [&](const Blk& k) {
@@ -1257,7 +1256,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   blk_step<LIST>(nn, q);
   blk_step<LIST>(nn, q);
   if (bbeg < bend) {
-    fetch(cur);
+    fetch(cur, 0, kW32PF);
     fetch_x(cur);
     stash(cur.mt);
   }
@@ -1266,8 +1265,10 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     const Blk k = cur;
     const int oA = k.oa.y, oB = k.ob.y;
     const bool more = blk + 1 < bend;
+    // the next block's W: the first half of its rows now, the second half once this block's
+    // products are done (so that they do not hold registers through the products)
     if (more) {
-      fetch(nxt);
+      fetch(nxt, 0, kW32PF / 2);
       fetch_x(nxt);
     }
     Blk nf = nn;
@@ -1285,6 +1286,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
         __builtin_amdgcn_sched_barrier(0);
       }
     }
+    if (more) fetch(nxt, kW32PF / 2, kW32PF);
     __syncthreads();  // every wavefront is done with W
     if (mm) {
 #pragma unroll
@@ -1333,6 +1335,20 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     blk_step<LIST>(nn, q);
     __syncthreads();
   }
+}
+
+// The dense walk is compiled without an occupancy request: the allocator then fits it in 168
+// registers (three wavefronts per SIMD) without spilling, which it does not when asked for
+// three wavefronts explicitly.  The block-list walk needs the request to stay at three.
+__global__ __launch_bounds__(192) void s_bf16x3(const float2* __restrict__ GR, const float2* __restrict__ WR,
+                                                double2* __restrict__ S, const float* __restrict__ CpA,
+                                                const float* __restrict__ CpB, const PairArgs q) {
+  s_bf16x3_body<false>(GR, WR, S, CpA, CpB, q);
+}
+__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3_list(
+    const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
+    const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
+  s_bf16x3_body<true>(GR, WR, S, CpA, CpB, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -1942,7 +1958,7 @@ bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
     hipLaunchKernelGGL((s_mfma<float, float2, true>), dim3(grid_for(q.nblocks)), dim3(kSThreads), 0, s,
                        (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (p == GW_BF16X3 && si)
-    hipLaunchKernelGGL(s_bf16x3<true>, dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR, (const float2*)WR,
+    hipLaunchKernelGGL(s_bf16x3_list, dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR, (const float2*)WR,
                        (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (si)
     hipLaunchKernelGGL((s_mfma32<4, 16, 3, true>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,

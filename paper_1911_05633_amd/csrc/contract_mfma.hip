@@ -1110,9 +1110,12 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // Every FP32 operand x is split as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi),
 // and a product a b is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo lo term, of
 // relative size 2^-16, is dropped), accumulated in FP32 by v_mfma_f32_16x16x32_bf16.
-// Same blocks, walk, prefetch and FP64 unfold as s_mfma32; the W block is split once
-// when it is staged and sits in LDS as four bf16 planes (re hi, re lo, im hi, im lo;
-// row stride 72: the 16-byte A-operand reads of eight lanes hit distinct banks).
+// Same blocks and walk as s_mfma32, with four wavefronts: waves 0-2 own the 16-column pair
+// tiles of B in the products, all four load and stage W (the next block's W is prefetched in
+// two halves, the second after this block's products) and share the orbital unfold (three
+// lanes per output, one third of a' each).  The W block is split once when it is staged and
+// sits in LDS as four bf16 planes (re hi, re lo, im hi, im lo; row stride 72: the 16-byte
+// A-operand reads of eight lanes hit distinct banks).
 // GEMM1 (Z = W C~_B) takes K = 64 in two 32-deep steps.  GEMM2 (K = C~_A^T Z) takes
 // its K = 64 product functions I in two steps of two I tiles: the D fragments of GEMM1
 // for tiles 2s and 2s + 1 (rows 4 g + j in register j of lane group g) are split in
@@ -1120,6 +1123,10 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // C~_A is stored in LDS in that slot order.  Shapes: 9-orbital species with
 // 49..64 product functions on both atoms.
 // ---------------------------------------------------------------------------
+
+constexpr int kSBWaves = 4;                                   // wavefronts of the BF16-split Sigma kernel
+constexpr int kSBThreads = 64 * kSBWaves;
+constexpr int kWBPF = (kMP + kSBWaves - 1) / kSBWaves;        // prefetched W values per thread
 
 template <bool LIST>
 __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, const float2* __restrict__ WR,
@@ -1132,7 +1139,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const bool mm = 16 * w < q.nppB;
   // C~_A in GEMM2 slot order, split
-  for (int i = tid; i < 2 * kPL * 32; i += kS32Threads) {
+  for (int i = tid; i < 2 * kPL * 32; i += kSBThreads) {
     const int st = i / (kPL * 32), r = i - st * kPL * 32, p = r / 32, slot = r - p * 32;
     const int g = slot >> 3, e = slot & 7;
     const int I = 16 * (2 * st + (e >> 2)) + 4 * g + (e & 3);
@@ -1157,18 +1164,20 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     }
   __builtin_amdgcn_s_waitcnt(0);
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
-  const int half_a = (q.nA + 1) / 2;
-  const int uo = tid >> 1, uh = tid & 1;
-  float2 wreg[kW32PF];
+  // orbital unfold: lanes 3 j .. 3 j + 2 of wavefront w (j < 21) share output 21 w + j, each
+  // summing one third of the a' range
+  const int third = (q.nA + 2) / 3;
+  const int uo = 21 * w + lane / 3, uh = lane - 3 * (lane / 3);
+  float2 wreg[kWBPF];
   float2 xr;
   const bool lane_ok = lane < q.mB;
-  // rows w + 3 u of W for u in [u0, u1)
+  // rows w + 4 u of W for u in [u0, u1)
   auto fetch = [&](const Blk& k, int u0, int u1) {
     const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(k.oa.x + w) * q.Np + k.ob.x + lane;
-    const long long step = 3LL * q.Np;
+    const long long step = (long long)kSBWaves * q.Np;
 #pragma unroll
-    for (int u = 0; u < kW32PF; ++u)
-      if (u >= u0 && u < u1) wreg[u] = ldraw(p + u * step, WR, lane_ok && w + 3 * u < q.mA);
+    for (int u = 0; u < kWBPF; ++u)
+      if (u >= u0 && u < u1) wreg[u] = ldraw(p + u * step, WR, lane_ok && w + kSBWaves * u < q.mA);
   };
   const bool xok = tid < q.nA * q.nB;
   auto fetch_x = [&](const Blk& k) {
@@ -1178,8 +1187,8 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   // mt: product functions kept by the block whose W is staged (W outside them is zero)
   auto stash = [&](int mt) {
 #pragma unroll
-    for (int u = 0; u < kW32PF; ++u) {
-      const int r = w + 3 * u;
+    for (int u = 0; u < kWBPF; ++u) {
+      const int r = w + kSBWaves * u;
       if (r < kMP) {
         const bool tier = !LIST || (r < (mt & 0xffff) && lane < (mt >> 16));
         const float2 v = keep(wreg[u], r < q.mA && lane_ok && tier);
@@ -1256,7 +1265,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   blk_step<LIST>(nn, q);
   blk_step<LIST>(nn, q);
   if (bbeg < bend) {
-    fetch(cur, 0, kW32PF);
+    fetch(cur, 0, kWBPF);
     fetch_x(cur);
     stash(cur.mt);
   }
@@ -1268,7 +1277,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     // the next block's W: the first half of its rows now, the second half once this block's
     // products are done (so that they do not hold registers through the products)
     if (more) {
-      fetch(nxt, 0, kW32PF / 2);
+      fetch(nxt, 0, kWBPF / 2);
       fetch_x(nxt);
     }
     Blk nf = nn;
@@ -1286,7 +1295,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-    if (more) fetch(nxt, kW32PF / 2, kW32PF);
+    if (more) fetch(nxt, kWBPF / 2, kWBPF);
     __syncthreads();  // every wavefront is done with W
     if (mm) {
 #pragma unroll
@@ -1297,10 +1306,10 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     }
     __syncthreads();
     double sr = 0, si = 0;
-    const bool live = uo < q.nA * q.nB;
+    const bool live = lane < 63 && uo < q.nA * q.nB;
     if (live) {
       const int a = uo / q.nB, bb = uo - a * q.nB;
-      const int a0 = uh ? half_a : 0, a1 = uh ? q.nA : half_a;
+      const int a0 = uh * third, a1 = a0 + third < q.nA ? a0 + third : q.nA;
       int pb[9];
 #pragma unroll
       for (int bp = 0; bp < 9; ++bp) pb[bp] = bp < q.nB ? pair_index(bb, bp, q.nB) : 0;
@@ -1322,8 +1331,9 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
         si += (double)pi[0] + (double)pi[1];
       }
     }
-    sr += __shfl_xor(sr, 1);
-    si += __shfl_xor(si, 1);
+    // the three thirds meet in the first lane of the triple
+    sr += __shfl_down(sr, 1) + __shfl_down(sr, 2);
+    si += __shfl_down(si, 1) + __shfl_down(si, 2);
     __syncthreads();  // K and X no longer read
     if (more) stash(nxt.mt);
     if (live && uh == 0) {
@@ -1340,12 +1350,12 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
 // The dense walk is compiled without an occupancy request: the allocator then fits it in 168
 // registers (three wavefronts per SIMD) without spilling, which it does not when asked for
 // three wavefronts explicitly.  The block-list walk needs the request to stay at three.
-__global__ __launch_bounds__(192) void s_bf16x3(const float2* __restrict__ GR, const float2* __restrict__ WR,
+__global__ __launch_bounds__(256) void s_bf16x3(const float2* __restrict__ GR, const float2* __restrict__ WR,
                                                 double2* __restrict__ S, const float* __restrict__ CpA,
                                                 const float* __restrict__ CpB, const PairArgs q) {
   s_bf16x3_body<false>(GR, WR, S, CpA, CpB, q);
 }
-__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3_list(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3_list(
     const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
     const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
   s_bf16x3_body<true>(GR, WR, S, CpA, CpB, q);
@@ -1889,7 +1899,7 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
     hipLaunchKernelGGL((s_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);
   else if (p == GW_BF16X3 && A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)
-    hipLaunchKernelGGL(s_bf16x3, dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR, (const float2*)WR,
+    hipLaunchKernelGGL(s_bf16x3, dim3(grid32), dim3(kSBThreads), 0, s, (const float2*)GR, (const float2*)WR,
                        (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)  // n = 9 with m in (48, 64]: the Si-like species
     hipLaunchKernelGGL((s_mfma32<4, 16, 3>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
@@ -1958,7 +1968,7 @@ bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
     hipLaunchKernelGGL((s_mfma<float, float2, true>), dim3(grid_for(q.nblocks)), dim3(kSThreads), 0, s,
                        (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (p == GW_BF16X3 && si)
-    hipLaunchKernelGGL(s_bf16x3_list, dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR, (const float2*)WR,
+    hipLaunchKernelGGL(s_bf16x3_list, dim3(grid32), dim3(kSBThreads), 0, s, (const float2*)GR, (const float2*)WR,
                        (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (si)
     hipLaunchKernelGGL((s_mfma32<4, 16, 3, true>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,

@@ -602,12 +602,15 @@ __global__ __launch_bounds__(512, 1) void drain_pp(const double2* __restrict__ T
 //                N_R = 8); the loads of chunk k + 1 go out one unit per m tile, so that loads
 //                and stores spread over the product phase and land before the next fill;
 //   barrier (y is free again).
-// Shapes: N_R in {2, 4, 8}, n_tau <= 48, n_omega <= 16 MT.
+// Shapes: N_R in {2, 4, 8}, n_tau <= 64, n_omega <= 16 MT <= 64.  A rows are padded by one
+// entry (the 16 rows of an A operand read then fall in distinct banks); where that does not fit
+// LDS (n_tau > 56 with four m tiles) they are stored unpadded with their columns XOR-swizzled by
+// m % 16 instead, and at n_tau = n_omega = 64 y and A fill the 160 KiB of LDS exactly.
 constexpr int kWideThreads = 512;
 constexpr int kWideCols = 256;
-constexpr int kWideMaxTau = 48;
+constexpr int kWideMaxTau = 64;
 
-template <int N1, int N2, int N3, int MT>
+template <int N1, int N2, int N3, int MT, bool SWZ>
 __global__ __launch_bounds__(512, 1) void drain_wide(const double2* __restrict__ T, int n_omega, int n_tau,
                                                      double sgn, const float2* in, float2* out, long long n2,
                                                      long long nchunks) {
@@ -619,15 +622,18 @@ __global__ __launch_bounds__(512, 1) void drain_wide(const double2* __restrict__
   extern __shared__ double2 lds[];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int nt8 = (n_tau + 7) & ~7;
-  const int ld_t = nt8 + 1;
+  // A rows: padded to nt8 + 1, or (SWZ) of length n_tau rounded up to 16 with entry t of row m
+  // at t ^ (m % 16)
+  constexpr int swz = SWZ ? 15 : 0;
+  const int ld_t = SWZ ? (n_tau + 15) & ~15 : nt8 + 1;
   const int half = (n_tau + 1) / 2;
   const int rows = (n_tau & 1) ? n_tau + 1 : n_tau;  // rows of y that fill() writes
   float2* Y = reinterpret_cast<float2*>(lds);         // [nt8][NCP]
-  double* As = reinterpret_cast<double*>(Y + nt8 * NCP);  // [16 MT][ld_t]
+  double* As = reinterpret_cast<double*>(Y + nt8 * NCP);  // [16 MT][ld_t], columns swizzled
   // K row t of the paired form: Re T[m][t] for t < half, Im T[m][n_tau - 1 - t] for half <= t <
   // n_tau, Im T[m][half - 1] at t = n_tau for odd n_tau; zero beyond
   for (int i = tid; i < 16 * MT * ld_t; i += kWideThreads) {
-    const int m = i / ld_t, t = i - m * ld_t;
+    const int m = i / ld_t, t = (i - m * ld_t) ^ (m & swz);
     double a = 0.0;
     if (m < n_omega) {
       if (t < half) a = T[(long long)m * n_tau + t].x;
@@ -715,7 +721,7 @@ __global__ __launch_bounds__(512, 1) void drain_wide(const double2* __restrict__
       for (int ks = 0; ks < ksn; ++ks) {
         const int t = 4 * ks + lk;
         const float2 y0 = Y[t * NCP + 32 * w + li], y1 = Y[t * NCP + 32 * w + 16 + li];
-        const double a = As[(16 * i + li) * ld_t + t];
+        const double a = As[(16 * i + li) * ld_t + (t ^ (li & swz))];
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)y0.x, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)y0.y, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)y1.x, acc[1][0], 0, 0, 0);
@@ -806,7 +812,7 @@ void run_drain(const double2* T, int n_omega, int n_tau, int parity, const TI* i
   // wide-chunk kernel for the paired drain in complex64 storage (the mixed path's P drain)
   if constexpr (NR >= 2 && NR <= 8 && kWideCols % NR == 0 && std::is_same<TI, float2>::value &&
                 std::is_same<TO, float2>::value) {
-    if (parity != 0 && n_tau <= kWideMaxTau && n_omega <= 48 && !wide_disabled()) {
+    if (parity != 0 && n_tau <= kWideMaxTau && n_omega <= 64 && !wide_disabled()) {
       constexpr int CBW = kWideCols / NR;
       const long long nchunks = (n2 + CBW - 1) / CBW;
       const int nt8 = (n_tau + 7) & ~7;
@@ -815,15 +821,18 @@ void run_drain(const double2* T, int n_omega, int n_tau, int parity, const TI* i
           hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
         n_cu = 256;
       const long long grid = nchunks < n_cu ? nchunks : n_cu;
-      auto go = [&](auto kern, int mt) {
-        const size_t lds = (size_t)nt8 * kWideCols * sizeof(float2) + (size_t)16 * mt * (nt8 + 1) * sizeof(double);
+      const size_t ly = (size_t)nt8 * kWideCols * sizeof(float2);
+      auto go = [&](auto kern, int mt, bool swz) {
+        const size_t lds = ly + (size_t)16 * mt * (swz ? (n_tau + 15) & ~15 : nt8 + 1) * sizeof(double);
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kWideThreads), lds, s, T, n_omega, n_tau,
                            parity < 0 ? -1.0 : 1.0, (const float2*)in, (float2*)out, n2, nchunks);
       };
-      if (MT == 1) go(drain_wide<N1, N2, N3, 1>, 1);
-      else if (MT == 2) go(drain_wide<N1, N2, N3, 2>, 2);
-      else go(drain_wide<N1, N2, N3, 3>, 3);
+      if (MT == 1) go(drain_wide<N1, N2, N3, 1, false>, 1, false);
+      else if (MT == 2) go(drain_wide<N1, N2, N3, 2, false>, 2, false);
+      else if (MT == 3) go(drain_wide<N1, N2, N3, 3, false>, 3, false);
+      else if (ly + (size_t)64 * (nt8 + 1) * sizeof(double) <= 160 * 1024) go(drain_wide<N1, N2, N3, 4, false>, 4, false);
+      else go(drain_wide<N1, N2, N3, 4, true>, 4, true);
       return;
     }
   }

@@ -1,13 +1,14 @@
 """GPU parity of the wide-chunk paired drain (complex64 in and out, parity +1 / -1).
 
 The drain with the tau mirror folded in runs, for complex64 storage, meshes of 2, 4 and 8
-points, n_tau <= 48 and n_omega <= 48, on a kernel that moves 256 columns (256 / N_R elements
+points, n_tau <= 64 and n_omega <= 64, on a kernel that moves 256 columns (256 / N_R elements
 of every row) per chunk and holds the paired, R -> k transformed y in complex64 in LDS.  Each
 case runs it and the two-stream ping-pong kernel (selected by GWR_DRAIN=pingpong) on the same
 input, in place as the step does, and checks both against the oracle's r_to_k followed by the
 Filon tau -> Matsubara matrix of Eqs. (5) and (8) on the complex64 values the kernels read.
 Shapes give several chunks per workgroup, a ragged last chunk, odd n_tau (the self-mirrored
-middle row) and n_omega below n_tau (one, two and three 16-row m tiles).  Bar: 1e-6 of the
+middle row) and n_omega below n_tau (one to four 16-row m tiles; at n_tau = n_omega = 64 the
+kernel's y and A fill LDS exactly).  Bar: 1e-6 of the
 largest output (complex64 storage; rounding y to complex64 adds about 1e-7).
 """
 import os
@@ -39,6 +40,8 @@ CASES = {
     "m4_t47": ((2, 2, 1), 47, 7, 100, 3),
     "m2_t48": ((2, 1, 1), 48, 6, 100, 2),
     "m2_t5": ((2, 1, 1), 5, 3, 29, 2),
+    "m8_t64": ((2, 2, 2), 64, 4, 70, 2),
+    "m4_t61": ((2, 2, 1), 61, 5, 90, 2),
 }
 
 

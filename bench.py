@@ -12,8 +12,9 @@ A step is the whole path on one synthetic cell with inputs resident in HBM:
     -> drain (R->k, tau->Matsubara) of P and of Sigma -> electron count.
 The metric is the algorithmic P + Sigma GFLOP/s of the whole step.  The default
 (mixed) path stores G, W, P as complex64 and runs both contractions on the BF16
-matrix cores with split-precision (hi + lo) products and FP32 accumulation; the lattice and Matsubara transforms, the Sigma orbital sums and
-the electron count are FP64.  The FP32 and the plain FP64 paths are timed after it
+matrix cores with split-precision (hi + lo) products and FP32 accumulation; the lattice and
+Matsubara transforms and the electron count are FP64, and the Sigma orbital sums run in FP32 per
+row of nine terms and in FP64 across rows.  The FP32 and the plain FP64 paths are timed after it
 on the same inputs, each with its error on the oracle's sample.  One JSON line is printed with a roofline entry for the dominant kernel
 (timed with events on the launch stream) and the CPU oracle timed on a bounded
 sample, whose outputs also give the error of the timed path.
@@ -37,14 +38,12 @@ HBM_PEAK = 8.0e12
 # the summaries are in profiles/).  Keyed by (kernel, precision); valid only while the
 # source file that defines the kernel has the recorded SHA-256 prefix, else reported null.
 TRAFFIC = {
-    ("Sigma", "bf16x3"): {"bytes": 75.49e9 + 11.87e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
-                          "sha256": "2430dc4ca39c3fd5"},
+    ("Sigma", "bf16x3"): {"bytes": 59.03e9 + 3.33e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
+                          "sha256": "ecc3d9495437d789"},
     ("P", "bf16x3"): {"bytes": 3.09e9 + 58.85e9, "source": "paper_1911_05633_amd/csrc/contract_mfma.hip",
-                      "sha256": "2430dc4ca39c3fd5"},
-    ("drain_P", "bf16x3"): {"bytes": 64.26e9 + 78.59e9, "source": "paper_1911_05633_amd/csrc/omega_kernels.h",
-                            "sha256": "c18cd167d389bbc1"},
-    ("drain_P", "fp32"): {"bytes": 64.73e9 + 78.24e9, "source": "paper_1911_05633_amd/csrc/omega_kernels.h",
-                          "sha256": "c18cd167d389bbc1"},
+                      "sha256": "ecc3d9495437d789"},
+    ("drain_P", "bf16x3"): {"bytes": 57.33e9 + 57.33e9, "source": "paper_1911_05633_amd/csrc/omega_kernels.h",
+                            "sha256": "e263b1c8de584bc2"},
     ("k2r", "bf16x3"): {"bytes": 2.58e9 + 1.29e9, "source": "paper_1911_05633_amd/csrc/fourier.hip",
                         "sha256": "a5af6e76c96c7ef9"},
 }

@@ -449,6 +449,12 @@ constexpr int kWBS = 72;                    // bf16 row stride of a W plane
 constexpr int kWBP = kMP * kWBS;            // bf16 elements per W plane
 constexpr int kCBS = 40;                    // bf16 per (plane, step, p) row of C~_A: 4 groups of 8 + pad
 
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+// bf16(x) in the low half, bf16(y) in the high half (round to nearest even)
+__device__ __forceinline__ unsigned pack_bf16x2(float x, float y) {
+  const bf2 h = {(__bf16)x, (__bf16)y};
+  return __builtin_bit_cast(unsigned, h);
+}
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
@@ -1126,7 +1132,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 
 constexpr int kSBWaves = 4;                                   // wavefronts of the BF16-split Sigma kernel
 constexpr int kSBThreads = 64 * kSBWaves;
-constexpr int kWBPF = (kMP + kSBWaves - 1) / kSBWaves;        // prefetched W values per thread
+constexpr int kWBU = kMP / (2 * kSBWaves);                    // W row steps per thread (two columns each)
 
 template <bool LIST>
 __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, const float2* __restrict__ WR,
@@ -1168,16 +1174,24 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   // summing one third of the a' range
   const int third = (q.nA + 2) / 3;
   const int uo = 21 * w + lane / 3, uh = lane - 3 * (lane / 3);
-  float2 wreg[kWBPF];
+  // W staging: lane = 32 ro + c holds columns 2 c, 2 c + 1 of rows 8 u + 2 w + ro, so that each
+  // split plane takes one 4-byte write per lane and column pair
+  float2 wreg[kWBU][2];
   float2 xr;
-  const bool lane_ok = lane < q.mB;
-  // rows w + 4 u of W for u in [u0, u1)
+  const int wro = lane >> 5, wc = 2 * (lane & 31);
+  const bool c0_ok = wc < q.mB, c1_ok = wc + 1 < q.mB;
+  // rows of steps u in [u0, u1)
   auto fetch = [&](const Blk& k, int u0, int u1) {
-    const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(k.oa.x + w) * q.Np + k.ob.x + lane;
-    const long long step = (long long)kSBWaves * q.Np;
+    const float2* p = WR + ((long long)k.t * q.NR + k.R) * slp + (long long)(k.oa.x + 2 * w + wro) * q.Np +
+                      k.ob.x + wc;
+    const long long step = 8LL * q.Np;
 #pragma unroll
-    for (int u = 0; u < kWBPF; ++u)
-      if (u >= u0 && u < u1) wreg[u] = ldraw(p + u * step, WR, lane_ok && w + kSBWaves * u < q.mA);
+    for (int u = 0; u < kWBU; ++u)
+      if (u >= u0 && u < u1) {
+        const bool row_ok = 8 * u + 2 * w + wro < q.mA;
+        wreg[u][0] = ldraw(p + u * step, WR, row_ok && c0_ok);
+        wreg[u][1] = ldraw(p + u * step + 1, WR, row_ok && c1_ok);
+      }
   };
   const bool xok = tid < q.nA * q.nB;
   auto fetch_x = [&](const Blk& k) {
@@ -1187,19 +1201,19 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   // mt: product functions kept by the block whose W is staged (W outside them is zero)
   auto stash = [&](int mt) {
 #pragma unroll
-    for (int u = 0; u < kWBPF; ++u) {
-      const int r = w + kSBWaves * u;
-      if (r < kMP) {
-        const bool tier = !LIST || (r < (mt & 0xffff) && lane < (mt >> 16));
-        const float2 v = keep(wreg[u], r < q.mA && lane_ok && tier);
-        __bf16 h, l;
-        split_bf16(v.x, h, l);
-        Wp[0 * kWBP + r * kWBS + lane] = h;
-        Wp[1 * kWBP + r * kWBS + lane] = l;
-        split_bf16(v.y, h, l);
-        Wp[2 * kWBP + r * kWBS + lane] = h;
-        Wp[3 * kWBP + r * kWBS + lane] = l;
-      }
+    for (int u = 0; u < kWBU; ++u) {
+      const int r = 8 * u + 2 * w + wro;
+      const bool row_ok = r < q.mA && (!LIST || r < (mt & 0xffff));
+      const float2 v0 = keep(wreg[u][0], row_ok && c0_ok && (!LIST || wc < (mt >> 16)));
+      const float2 v1 = keep(wreg[u][1], row_ok && c1_ok && (!LIST || wc + 1 < (mt >> 16)));
+      const unsigned rh = pack_bf16x2(v0.x, v1.x), ih = pack_bf16x2(v0.y, v1.y);
+      const unsigned rl = pack_bf16x2(v0.x - __uint_as_float(rh << 16), v1.x - __uint_as_float(rh & 0xffff0000u));
+      const unsigned il = pack_bf16x2(v0.y - __uint_as_float(ih << 16), v1.y - __uint_as_float(ih & 0xffff0000u));
+      const int o = r * kWBS + wc;
+      *reinterpret_cast<unsigned*>(&Wp[0 * kWBP + o]) = rh;
+      *reinterpret_cast<unsigned*>(&Wp[1 * kWBP + o]) = rl;
+      *reinterpret_cast<unsigned*>(&Wp[2 * kWBP + o]) = ih;
+      *reinterpret_cast<unsigned*>(&Wp[3 * kWBP + o]) = il;
     }
     if (xok) Xs[tid] = xr;
   };
@@ -1265,7 +1279,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   blk_step<LIST>(nn, q);
   blk_step<LIST>(nn, q);
   if (bbeg < bend) {
-    fetch(cur, 0, kWBPF);
+    fetch(cur, 0, kWBU);
     fetch_x(cur);
     stash(cur.mt);
   }
@@ -1277,7 +1291,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     // the next block's W: the first half of its rows now, the second half once this block's
     // products are done (so that they do not hold registers through the products)
     if (more) {
-      fetch(nxt, 0, kWBPF / 2);
+      fetch(nxt, 0, kWBU / 2);
       fetch_x(nxt);
     }
     Blk nf = nn;
@@ -1295,7 +1309,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-    if (more) fetch(nxt, kWBPF / 2, kWBPF);
+    if (more) fetch(nxt, kWBU / 2, kWBU);
     __syncthreads();  // every wavefront is done with W
     if (mm) {
 #pragma unroll

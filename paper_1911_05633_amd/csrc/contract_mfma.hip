@@ -455,6 +455,12 @@ __device__ __forceinline__ unsigned pack_bf16x2(float x, float y) {
   const bf2 h = {(__bf16)x, (__bf16)y};
   return __builtin_bit_cast(unsigned, h);
 }
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+// split_bf16 of x and y at once: hi and lo packed as (x, y)
+__device__ __forceinline__ void split_bf16x2(float x, float y, unsigned& hi, unsigned& lo) {
+  hi = pack_bf16x2(x, y);
+  lo = pack_bf16x2(x - __uint_as_float(hi << 16), y - __uint_as_float(hi & 0xffff0000u));
+}
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
@@ -1237,23 +1243,20 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   };
   // GEMM2 step st: acc2[m][part] += C~_A^T Z over I tiles 2 st, 2 st + 1
   auto gemm2 = [&](int st, const f4& zr0, const f4& zi0, const f4& zr1, const f4& zi1, f4 (&acc2)[3][2]) {
-    bf8 brh, brl, bih, bil;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      __bf16 h, l;
-      split_bf16(zr0[e], h, l);
-      brh[e] = h;
-      brl[e] = l;
-      split_bf16(zr1[e], h, l);
-      brh[4 + e] = h;
-      brl[4 + e] = l;
-      split_bf16(zi0[e], h, l);
-      bih[e] = h;
-      bil[e] = l;
-      split_bf16(zi1[e], h, l);
-      bih[4 + e] = h;
-      bil[4 + e] = l;
-    }
+    // split two K slots per conversion: dword d of the operand holds slots 2 d, 2 d + 1
+    unsigned rh[4], rl[4], ih[4], il[4];
+    split_bf16x2(zr0[0], zr0[1], rh[0], rl[0]);
+    split_bf16x2(zr0[2], zr0[3], rh[1], rl[1]);
+    split_bf16x2(zr1[0], zr1[1], rh[2], rl[2]);
+    split_bf16x2(zr1[2], zr1[3], rh[3], rl[3]);
+    split_bf16x2(zi0[0], zi0[1], ih[0], il[0]);
+    split_bf16x2(zi0[2], zi0[3], ih[1], il[1]);
+    split_bf16x2(zi1[0], zi1[1], ih[2], il[2]);
+    split_bf16x2(zi1[2], zi1[3], ih[3], il[3]);
+    const bf8 brh = __builtin_bit_cast(bf8, u4{rh[0], rh[1], rh[2], rh[3]});
+    const bf8 brl = __builtin_bit_cast(bf8, u4{rl[0], rl[1], rl[2], rl[3]});
+    const bf8 bih = __builtin_bit_cast(bf8, u4{ih[0], ih[1], ih[2], ih[3]});
+    const bf8 bil = __builtin_bit_cast(bf8, u4{il[0], il[1], il[2], il[3]});
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       const bf8 ah = *reinterpret_cast<const bf8*>(&Cap[((0 * 2 + st) * kPL + 16 * m + li) * kCBS + 8 * lk]);

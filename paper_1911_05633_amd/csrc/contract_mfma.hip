@@ -637,17 +637,13 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
         for (int pt = 0; pt < 2; ++pt) {
           const f4 d0 = gemm1(pt, 2 * st);
           const f4 d1 = st == 0 ? gemm1(pt, 1) : f4{0, 0, 0, 0};
-          bf8 bh, bl;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            __bf16 h, l;
-            split_bf16(d0[e], h, l);
-            bh[e] = h;
-            bl[e] = l;
-            split_bf16(d1[e], h, l);
-            bh[4 + e] = h;
-            bl[4 + e] = l;
-          }
+          unsigned hw[4], lw[4];  // dword d: K slots 2 d, 2 d + 1
+          split_bf16x2(d0[0], d0[1], hw[0], lw[0]);
+          split_bf16x2(d0[2], d0[3], hw[1], lw[1]);
+          split_bf16x2(d1[0], d1[1], hw[2], lw[2]);
+          split_bf16x2(d1[2], d1[3], hw[3], lw[3]);
+          const bf8 bh = __builtin_bit_cast(bf8, u4{hw[0], hw[1], hw[2], hw[3]});
+          const bf8 bl = __builtin_bit_cast(bf8, u4{lw[0], lw[1], lw[2], lw[3]});
 #pragma unroll
           for (int Jt = 0; Jt < 4; ++Jt) {
             const bf8 ah = *reinterpret_cast<const bf8*>(&Cbb[((0 * 2 + st) * kMP + 16 * Jt + li) * kCBB + 8 * lk]);

@@ -1653,7 +1653,7 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
   __shared__ CR Xs[kMaxOrb * kMaxOrb];     // X[a'][b'], 16 x 16 zero padded
   __shared__ CR Ms[16 * 16 * kGS];         // M[a'][J - 16 c][b] (row stride kGS)
   __shared__ CR Wc[kGMP * kGS];            // W[I][J - 16 c]
-  __shared__ double2 Sred[kMaxOrb * kMaxOrb];
+  __shared__ double2 Spart[kGThreads / 64][kMaxOrb * kMaxOrb];  // per-wavefront partial sums of S
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int nA = q.nA, nB = q.nB, mA = q.mA, mB = q.mB;
   const int nKI = q.mpA / 4, nCh = (mB + 15) / 16;
@@ -1715,6 +1715,19 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
       Xs[tid] = mk<RT>((double)v.x, (double)v.y);
     }
   };
+  // C^J operands of the M products (lane: J = 16 ch + 2 w + h, b' = 4 ks + lk, b = li); the same
+  // for every block, loaded one chunk ahead
+  RT cbr[2][4], cbn[2][4];
+  auto load_cb = [&](int ch, RT (&dst)[2][4]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int J = 16 * ch + 2 * w + h, bp = 4 * ks + lk;
+        dst[h][ks] = (J < mB && bp < nB && li < nB) ? CB[((long long)J * nB + bp) * nB + li] : RT(0);
+      }
+  };
+  load_cb(0, cbr);
   GBlk cur;
   gblk_start<PACK>(cur, bbeg < q.nblocks ? bbeg : 0, q);
   gblk_fill<PACK>(cur, q);
@@ -1745,6 +1758,7 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         load_w(nxt, 0);
         load_x(nxt);
       }
+      load_cb(ch + 1 < nChk ? ch + 1 : 0, cbn);
       // M[a'][J][b] for J = J0 + 2 w, J0 + 2 w + 1: A = X (row a' = li, k = b'),
       // B = C^J (k = b', n = b = li)
 #pragma unroll
@@ -1753,11 +1767,9 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         typename M::acc mr = {0, 0, 0, 0}, mi = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          const int bp = 4 * ks + lk;
-          const CR x = Xs[li * 16 + bp];
-          const RT cb = (J < mB && bp < nB && li < nB) ? CB[((long long)J * nB + bp) * nB + li] : RT(0);
-          mr = M::op(x.x, cb, mr);
-          mi = M::op(x.y, cb, mi);
+          const CR x = Xs[li * 16 + 4 * ks + lk];
+          mr = M::op(x.x, cbr[h][ks], mr);
+          mi = M::op(x.y, cbr[h][ks], mi);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) Ms[(M::drow(lk, j) * 16 + Jl) * kGS + li] = mk<RT>((double)mr[j], (double)mi[j]);
@@ -1798,34 +1810,41 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         }
       }
       __syncthreads();  // Wc and Ms are rewritten by the next chunk
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cbr[h][ks] = cbn[h][ks];
     }
-    // S_ab = -sum over a' of the accumulators (row b = drow(lk, j), column a = li), in FP64
-    for (int i = tid; i < 256; i += kGThreads) Sred[i] = make_double2(0.0, 0.0);
+    // S_ab = -sum over a' of the accumulators (row b = drow(lk, j), column a = li), in FP64: each
+    // wavefront adds its two a' and leaves one partial per element, then 256 threads add the 8
+    // partials
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double vr = 0.0, vi = 0.0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (w + 8 * u < nA) {
+          vr += (double)sr[u][j];
+          vi += (double)si[u][j];
+        }
+      Spart[w][li * 16 + M::drow(lk, j)] = make_double2(vr, vi);
+    }
     __syncthreads();
-    for (int r = 0; r < 8; ++r) {
-      if (w == r) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-          if (w + 8 * u < nA)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              double2& sv = Sred[li * 16 + M::drow(lk, j)];
-              sv.x += (double)sr[u][j];
-              sv.y += (double)si[u][j];
-            }
-      }
-      __syncthreads();
-    }
     if (tid < 256) {
       const int a = tid >> 4, b = tid & 15;
       if (a < nA && b < nB) {
-        const double2 v = Sred[tid];
-        S[((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + b] = make_double2(-v.x, -v.y);
+        double vr = 0.0, vi = 0.0;
+#pragma unroll
+        for (int r = 0; r < kGThreads / 64; ++r) {
+          vr += Spart[r][tid].x;
+          vi += Spart[r][tid].y;
+        }
+        S[((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + b] = make_double2(-vr, -vi);
       }
     }
     cur = nxt;
     gblk_step<PACK>(nxt, q);
-    __syncthreads();  // Xs and Sred are rewritten by the next block
+    __syncthreads();  // Xs and Spart are rewritten by the next block
   }
 }
 

@@ -155,7 +155,10 @@ gw_status gw_tau2omega(const gw_cell* cell, const void* T, int n_omega, int pari
                        gw_dtype in_type, void* out, gw_dtype out_type, int basis, void* stream);
 
 /* R -> k followed by tau -> Matsubara in one pass over HBM (product of the two
- * operators above; same argument rules, parity included). */
+ * operators above; same argument rules, parity included).  For complex64 in and out with
+ * parity +1 or -1 (the mixed paths' P drain), the paired, R -> k transformed columns are formed
+ * in FP64 and held on chip as complex64 (the storage precision of in and out) before the FP64
+ * tau contraction; the other cases stay FP64 throughout. */
 gw_status gw_drain(const gw_cell* cell, const void* T, int n_omega, int parity, const void* in,
                    gw_dtype in_type, void* out, gw_dtype out_type, int basis, void* stream);
 

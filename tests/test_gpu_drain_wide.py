@@ -7,8 +7,8 @@ case runs it and the two-stream ping-pong kernel (selected by GWR_DRAIN=pingpong
 input, in place as the step does, and checks both against the oracle's r_to_k followed by the
 Filon tau -> Matsubara matrix of Eqs. (5) and (8) on the complex64 values the kernels read.
 Shapes give several chunks per workgroup, a ragged last chunk, odd n_tau (the self-mirrored
-middle row) and n_omega below n_tau (one to four 16-row m tiles; at n_tau = n_omega = 64 the
-kernel's y and A fill LDS exactly).  Bar: 1e-6 of the
+middle row), n_omega below and above n_tau (one to four 16-row m tiles; at n_tau = n_omega = 64
+the kernel's y and A fill LDS exactly).  Bar: 1e-6 of the
 largest output (complex64 storage; rounding y to complex64 adds about 1e-7).
 """
 import os
@@ -51,7 +51,8 @@ def _run(g, cell, Td, F, basis, parity, pingpong):
     if pingpong:
         os.environ["GWR_DRAIN"] = "pingpong"
     try:
-        g.gw_drain(cell, Td, x, x, basis=basis, parity=parity)
+        n_tau = cell.n_tau
+        g.gw_drain(cell, Td, x[:n_tau], x, basis=basis, parity=parity)  # in place: in is out's first n_tau rows
         torch.cuda.synchronize()
     finally:
         os.environ.pop("GWR_DRAIN", None)
@@ -59,7 +60,10 @@ def _run(g, cell, Td, F, basis, parity, pingpong):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("basis,parity,n_omega", [(1, 1, None), (1, 1, 19), (0, -1, None), (0, -1, 3)])
+# n_omega: None = n_tau, -1 = min(2 n_tau, 64) (more frequencies than tau points: the output rows
+# outrun the input rows in place)
+@pytest.mark.parametrize("basis,parity,n_omega",
+                         [(1, 1, None), (1, 1, 19), (1, 1, -1), (0, -1, None), (0, -1, 3), (0, -1, -1)])
 def test_drain_wide(name, basis, parity, n_omega):
     import torch
     import paper_1911_05633_amd as g
@@ -70,11 +74,10 @@ def test_drain_wide(name, basis, parity, n_omega):
     n = spec.N_orb if basis == 0 else spec.N_pb
     kind = "fermionic" if basis == 0 else "bosonic"
     tau = sc.tau_grid(spec)
-    w = g.matsubara(n_tau, spec.beta, kind)
-    if n_omega is not None:
-        w = w[:min(n_omega, len(w))]
-    freqs = (oracle.fermionic_frequencies(n_tau, spec.beta) if kind == "fermionic"
-             else oracle.bosonic_frequencies(n_tau, spec.beta))[:len(w)]
+    n_w = n_tau if n_omega is None else (min(2 * n_tau, 64) if n_omega < 0 else min(n_omega, n_tau))
+    w = g.matsubara(n_w, spec.beta, kind)
+    freqs = (oracle.fermionic_frequencies(n_w, spec.beta) if kind == "fermionic"
+             else oracle.bosonic_frequencies(n_w, spec.beta))
     Td = torch.from_numpy(np.ascontiguousarray(g.gw_tau2omega_matrix(tau, w))).cuda()
     rows = max(n_tau, len(w))
     F = np.zeros((rows, spec.N_R, n, n), dtype=np.complex64)

@@ -1121,7 +1121,8 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // Same blocks and walk as s_mfma32, with four wavefronts: waves 0-2 own the 16-column pair
 // tiles of B in the products, all four load and stage W (the next block's W is prefetched in
 // two halves, the second after this block's products) and share the orbital unfold (three
-// lanes per output, one third of a' each).  The W block is split once when it is staged and
+// lanes per output, three of the nine rows a' each: X is staged as a zero-padded 9 x 9 tile,
+// so the unfold's 27 K and X reads per lane carry no branches and issue together).  The W block is split once when it is staged and
 // sits in LDS as four bf16 planes (re hi, re lo, im hi, im lo; row stride 72: the 16-byte
 // A-operand reads of eight lanes hit distinct banks).
 // GEMM1 (Z = W C~_B) takes K = 64 in two 32-deep steps.  GEMM2 (K = C~_A^T Z) takes
@@ -1173,8 +1174,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   __builtin_amdgcn_s_waitcnt(0);
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
   // orbital unfold: lanes 3 j .. 3 j + 2 of wavefront w (j < 21) share output 21 w + j, each
-  // summing one third of the a' range
-  const int third = (q.nA + 2) / 3;
+  // summing three of the nine (padded) rows a'
   const int uo = 21 * w + lane / 3, uh = lane - 3 * (lane / 3);
   // W staging: lane = 32 ro + c holds columns 2 c, 2 c + 1 of rows 8 u + 2 w + ro, so that each
   // split plane takes one 4-byte write per lane and column pair
@@ -1195,10 +1195,13 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
         wreg[u][1] = ldraw(p + u * step + 1, WR, row_ok && c1_ok);
       }
   };
-  const bool xok = tid < q.nA * q.nB;
+  // X sits in LDS as a 9 x 9 tile, zero outside its n_A x n_B corner, so that the unfold runs
+  // the same nine-by-nine loop (no branches) for every species of up to nine orbitals
+  const bool xok = tid < 81, xin = tid / 9 < q.nA && tid % 9 < q.nB;
   auto fetch_x = [&](const Blk& k) {
-    const int a = tid / q.nB, c = tid - a * q.nB;
-    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
+    const int a = tid / 9, c = tid - 9 * a;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR,
+               xok && xin);
   };
   // mt: product functions kept by the block whose W is staged (W outside them is zero)
   auto stash = [&](int mt) {
@@ -1217,7 +1220,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
       *reinterpret_cast<unsigned*>(&Wp[2 * kWBP + o]) = ih;
       *reinterpret_cast<unsigned*>(&Wp[3 * kWBP + o]) = il;
     }
-    if (xok) Xs[tid] = xr;
+    if (xok) Xs[tid] = keep(xr, xin);
   };
   // GEMM1 for I tile it: zr / zi = rows 16 it .. 16 it + 15 of Re / Im (W C~_B)
   auto gemm1 = [&](int it, f4& zr, f4& zi) {
@@ -1322,26 +1325,28 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     const bool live = lane < 63 && uo < q.nA * q.nB;
     if (live) {
       const int a = uo / q.nB, bb = uo - a * q.nB;
-      const int a0 = uh * third, a1 = a0 + third < q.nA ? a0 + third : q.nA;
+      // columns b' >= n_B and rows a' >= n_A meet zeros of X; their K indices are clamped
+      // to a valid entry
       int pb[9];
 #pragma unroll
-      for (int bp = 0; bp < 9; ++bp) pb[bp] = bp < q.nB ? pair_index(bb, bp, q.nB) : 0;
-      // each row a' summed in FP32 (nine products, two interleaved partial sums each for
-      // re and im), rows accumulated in FP64: the split products carry about 2^-16 relative
-      // error, far above the FP32 rounding of a nine-term row
-      for (int ap = a0; ap < a1; ++ap) {
-        const float2* Kr = Ks + pair_index(a, ap, q.nA) * kKS;
-        const float2* Xr = Xs + ap * q.nB;
+      for (int bp = 0; bp < 9; ++bp) pb[bp] = pair_index(bb, bp < q.nB ? bp : q.nB - 1, q.nB);
+      // lane third uh sums rows a' = 3 uh .. 3 uh + 2, each in FP32 (nine products, two
+      // interleaved partial sums each for re and im); the rows are accumulated in FP64: the
+      // split products carry about 2^-16 relative error, far above the FP32 rounding of a row
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int ap = 3 * uh + i;
+        const float2* Kr = Ks + pair_index(a, ap < q.nA ? ap : q.nA - 1, q.nA) * kKS;
+        const float2* Xr = Xs + 9 * ap;
         float pr[2] = {0.f, 0.f}, pi[2] = {0.f, 0.f};
 #pragma unroll
-        for (int bp = 0; bp < 9; ++bp)
-          if (bp < q.nB) {
-            const float2 kv = Kr[pb[bp]], x = Xr[bp];
-            pr[bp & 1] = fmaf(kv.x, x.x, fmaf(-kv.y, x.y, pr[bp & 1]));
-            pi[bp & 1] = fmaf(kv.x, x.y, fmaf(kv.y, x.x, pi[bp & 1]));
-          }
-        sr += (double)pr[0] + (double)pr[1];
-        si += (double)pi[0] + (double)pi[1];
+        for (int bp = 0; bp < 9; ++bp) {
+          const float2 kv = Kr[pb[bp]], x = Xr[bp];
+          pr[bp & 1] = fmaf(kv.x, x.x, fmaf(-kv.y, x.y, pr[bp & 1]));
+          pi[bp & 1] = fmaf(kv.x, x.y, fmaf(kv.y, x.x, pi[bp & 1]));
+        }
+        sr += (double)(pr[0] + pr[1]);
+        si += (double)(pi[0] + pi[1]);
       }
     }
     // the three thirds meet in the first lane of the triple
@@ -1360,12 +1365,11 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
   }
 }
 
-// The dense walk is compiled without an occupancy request: the allocator then fits it in 168
-// registers (three wavefronts per SIMD) without spilling, which it does not when asked for
-// three wavefronts explicitly.  The block-list walk needs the request to stay at three.
-__global__ __launch_bounds__(256) void s_bf16x3(const float2* __restrict__ GR, const float2* __restrict__ WR,
-                                                double2* __restrict__ S, const float* __restrict__ CpA,
-                                                const float* __restrict__ CpB, const PairArgs q) {
+// Both walks ask for three wavefronts per SIMD (three workgroups per CU, 52.9 KB of LDS each):
+// the allocator fits them in 168 registers without spilling.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3(
+    const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
+    const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
   s_bf16x3_body<false>(GR, WR, S, CpA, CpB, q);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3_list(

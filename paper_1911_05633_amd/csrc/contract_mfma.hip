@@ -739,7 +739,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   constexpr size_t kWbytes = 16 * kWS * sizeof(CR);
   constexpr size_t kKbytes = kPL * kKS * sizeof(CR);
   __shared__ __align__(16) unsigned char U[kWbytes > kKbytes ? kWbytes : kKbytes];
-  __shared__ CR Xs[81];
+  __shared__ CR Xs[90];  // X as a zero-padded 10 x 9 tile: fixed trip counts in the unfold
   __shared__ unsigned char pidA[81], pidB[81];
   CR* Wb = reinterpret_cast<CR*>(U);
   CR* Ks = reinterpret_cast<CR*>(U);
@@ -752,8 +752,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 #pragma unroll
   for (int ks = 0; ks < kKJ; ++ks) b1[ks] = (mm && ks < nKJ) ? CpB[(4 * ks + lk) * q.nppB + 16 * w + li] : RT(0);
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
-  // unfold: thread (o, half) sums a' over one half of atom A's orbitals
-  const int half_a = (q.nA + 1) / 2;
+  // unfold: thread (o, half) sums rows a' = 5 half .. 5 half + 4 (rows >= n_A are zero in X)
   const int uo = tid >> 1, uh = tid & 1;
 
   // block b: (tau, R, atoms) in counting order, or (tau, list entry) with LIST.  Dense: pA, pB
@@ -803,11 +802,11 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     wtile = it;
     if constexpr (LIST) wmt = k.mt;
   };
-  const bool xok = tid < q.nA * q.nB;
+  const bool xok = tid < 90, xin = tid / 9 < q.nA && tid % 9 < q.nB;
   auto fetch_x = [&](const SBlk& k) {
-    const int a = tid / q.nB, c = tid - a * q.nB;
+    const int a = tid / 9, c = tid - 9 * a;
     const int oa = LIST ? k.oA : q.orb_off[k.pA], ob = LIST ? k.oB : q.orb_off[k.pB];
-    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(oa + a) * q.No + ob + c, GR, xok);
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(oa + a) * q.No + ob + c, GR, xok && xin);
   };
   auto stash = [&]() {
 #pragma unroll
@@ -827,7 +826,10 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   if (blockIdx.x < q.nblocks) {
     fetch(decode(blockIdx.x), 0);
     fetch_x(decode(blockIdx.x));
-    if (tid < q.nA * q.nB) Xs[tid] = mk<RT>((double)xr.x, (double)xr.y);
+    if (xok) {
+      const CT xv = keep(xr, xin);
+      Xs[tid] = mk<RT>((double)xv.x, (double)xv.y);
+    }
     stash();
   }
   __syncthreads();
@@ -889,11 +891,14 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       const bool live = uo < q.nA * q.nB;
       if (live) {
         const int a = uo / q.nB, bb = uo - a * q.nB;
-        const int a0 = uh ? half_a : 0, a1 = uh ? q.nA : half_a;
-        for (int ap = a0; ap < a1; ++ap) {
-          const CR* Kr = Ks + pidA[a * q.nA + ap] * kKS;
-          for (int bp = 0; bp < q.nB; ++bp) {
-            const CR kv = Kr[pidB[bb * q.nB + bp]], x = Xs[ap * q.nB + bp];
+#pragma unroll 1
+        for (int i = 0; i < 5; ++i) {
+          const int ap = 5 * uh + i;
+          const CR* Kr = Ks + pidA[a * q.nA + (ap < q.nA ? ap : q.nA - 1)] * kKS;
+          const int bq = bb * q.nB;
+#pragma unroll
+          for (int bp = 0; bp < 9; ++bp) {
+            const CR kv = Kr[pidB[bq + (bp < q.nB ? bp : q.nB - 1)]], x = Xs[9 * ap + bp];
             sr += (double)kv.x * x.x - (double)kv.y * x.y;
             si += (double)kv.x * x.y + (double)kv.y * x.x;
           }
@@ -903,7 +908,10 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       si += __shfl_xor(si, 1);
       __syncthreads();  // K and X no longer read
       if (more) {
-        if (tid < q.nA * q.nB) Xs[tid] = mk<RT>((double)xr.x, (double)xr.y);
+        if (xok) {
+          const CT xv = keep(xr, xin);
+          Xs[tid] = mk<RT>((double)xv.x, (double)xv.y);
+        }
         stash();
       }
       if (live && uh == 0) {
@@ -938,7 +946,10 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
     const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
   __shared__ __align__(16) float2 Ub[kMP * kW32S];  // W block, then the K block
   __shared__ float Ca[kMP * kCA32S];
-  __shared__ float2 Xs[81];
+  // X as a zero-padded tile of 2 HR rows of nine (HR = rows a' per unfold half), so that
+  // the unfold loops have fixed trip counts
+  constexpr int HR = NMT >= 3 ? 5 : (NMT == 2 ? 4 : 3);
+  __shared__ float2 Xs[2 * HR * 9];
   float2* Wb = Ub;
   float2* Ks = Ub;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -956,7 +967,6 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
   // next block's W prefetch and serialise it with the matrix work.
   __builtin_amdgcn_s_waitcnt(0);
   const long long sl = (long long)q.No * q.No, slp = (long long)q.Np * q.Np;
-  const int half_a = (q.nA + 1) / 2;
   const int uo = tid >> 1, uh = tid & 1;
   // Blocks are walked in a contiguous range, so their (tau, R, iA, iB) indices advance by
   // counting (B fastest) and the atom offsets come from the per-species (pb, orb) tables;
@@ -974,10 +984,11 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       p += step;
     }
   };
-  const bool xok = tid < q.nA * q.nB;
+  const bool xok = tid < 2 * HR * 9, xin = tid / 9 < q.nA && tid % 9 < q.nB;
   auto fetch_x = [&](const Blk& k) {
-    const int a = tid / q.nB, c = tid - a * q.nB;
-    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR, xok);
+    const int a = tid / 9, c = tid - 9 * a;
+    xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR,
+               xok && xin);
   };
   // mt: product functions kept by the block whose W is staged (W outside them is zero)
   auto stash = [&](int mt) {
@@ -987,7 +998,7 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
       const bool tier = !LIST || (r < (mt & 0xffff) && lane < (mt >> 16));
       if (r < kMP) Wb[r * kW32S + lane] = keep(wreg[u], r < q.mA && lane_ok && tier);
     }
-    if (xok) Xs[tid] = xr;
+    if (xok) Xs[tid] = keep(xr, xin);
   };
   auto load_ca = [&](int it, float (&ca)[4][3]) {
 #pragma unroll
@@ -1076,26 +1087,27 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
             Ks[(16 * m + 4 * lk + j) * kKS + 16 * w + li] = make_float2(acc2[m][0][j], acc2[m][1][j]);
     }
     __syncthreads();
-    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'} in FP64; the two halves of the a'
-    // range sit in neighbouring lanes and are combined with one exchange
+    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'} in FP64; lane half uh takes rows
+    // a' = HR uh .. HR uh + HR - 1, and the halves meet in one exchange.  Rows a' >= n_A and
+    // columns b' >= n_B meet zeros of X; their K indices are clamped to a valid entry.
     double sr = 0, si = 0;
     const bool live = uo < q.nA * q.nB;
     if (live) {
       const int a = uo / q.nB, bb = uo - a * q.nB;
-      const int a0 = uh ? half_a : 0, a1 = uh ? q.nA : half_a;
       int pb[9];
 #pragma unroll
-      for (int bp = 0; bp < 9; ++bp) pb[bp] = bp < q.nB ? pair_index(bb, bp, q.nB) : 0;
-      for (int ap = a0; ap < a1; ++ap) {
-        const float2* Kr = Ks + pair_index(a, ap, q.nA) * kKS;
-        const float2* Xr = Xs + ap * q.nB;
+      for (int bp = 0; bp < 9; ++bp) pb[bp] = pair_index(bb, bp < q.nB ? bp : q.nB - 1, q.nB);
+#pragma unroll 1
+      for (int i = 0; i < HR; ++i) {
+        const int ap = HR * uh + i;
+        const float2* Kr = Ks + pair_index(a, ap < q.nA ? ap : q.nA - 1, q.nA) * kKS;
+        const float2* Xr = Xs + 9 * ap;
 #pragma unroll
-        for (int bp = 0; bp < 9; ++bp)
-          if (bp < q.nB) {
-            const float2 kv = Kr[pb[bp]], x = Xr[bp];
-            sr += (double)kv.x * x.x - (double)kv.y * x.y;
-            si += (double)kv.x * x.y + (double)kv.y * x.x;
-          }
+        for (int bp = 0; bp < 9; ++bp) {
+          const float2 kv = Kr[pb[bp]], x = Xr[bp];
+          sr += (double)kv.x * x.x - (double)kv.y * x.y;
+          si += (double)kv.x * x.y + (double)kv.y * x.x;
+        }
       }
     }
     sr += __shfl_xor(sr, 1);

@@ -1087,9 +1087,12 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
             Ks[(16 * m + 4 * lk + j) * kKS + 16 * w + li] = make_float2(acc2[m][0][j], acc2[m][1][j]);
     }
     __syncthreads();
-    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'} in FP64; lane half uh takes rows
+    // Sigma_ab = -sum_{a', b'} K[{a,a'}][{b,b'}] X_{a'b'}; lane half uh takes rows
     // a' = HR uh .. HR uh + HR - 1, and the halves meet in one exchange.  Rows a' >= n_A and
-    // columns b' >= n_B meet zeros of X; their K indices are clamped to a valid entry.
+    // columns b' >= n_B meet zeros of X; their K indices are clamped to a valid entry.  Each
+    // row (nine products) is summed in FP32 with two interleaved partial sums, the rows in
+    // FP64: K itself comes from FP32 products of 64-term sums, whose rounding is far above
+    // that of a nine-term FP32 row.
     double sr = 0, si = 0;
     const bool live = uo < q.nA * q.nB;
     if (live) {
@@ -1102,12 +1105,15 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
         const int ap = HR * uh + i;
         const float2* Kr = Ks + pair_index(a, ap < q.nA ? ap : q.nA - 1, q.nA) * kKS;
         const float2* Xr = Xs + 9 * ap;
+        float pr[2] = {0.f, 0.f}, pi[2] = {0.f, 0.f};
 #pragma unroll
         for (int bp = 0; bp < 9; ++bp) {
           const float2 kv = Kr[pb[bp]], x = Xr[bp];
-          sr += (double)kv.x * x.x - (double)kv.y * x.y;
-          si += (double)kv.x * x.y + (double)kv.y * x.x;
+          pr[bp & 1] = fmaf(kv.x, x.x, fmaf(-kv.y, x.y, pr[bp & 1]));
+          pi[bp & 1] = fmaf(kv.x, x.y, fmaf(kv.y, x.x, pi[bp & 1]));
         }
+        sr += (double)(pr[0] + pr[1]);
+        si += (double)(pi[0] + pi[1]);
       }
     }
     sr += __shfl_xor(sr, 1);

@@ -457,9 +457,13 @@ __device__ __forceinline__ unsigned pack_bf16x2(float x, float y) {
 }
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 // split_bf16 of x and y at once: hi and lo packed as (x, y)
+// (x's bf16 is moved to the high half with one byte permute: v_perm_b32 with selector
+// 0x01000c0c puts bytes 0, 1 of hi in bytes 2, 3 and zeros below, so that the compiler does
+// not convert x a second time to form it)
 __device__ __forceinline__ void split_bf16x2(float x, float y, unsigned& hi, unsigned& lo) {
   hi = pack_bf16x2(x, y);
-  lo = pack_bf16x2(x - __uint_as_float(hi << 16), y - __uint_as_float(hi & 0xffff0000u));
+  lo = pack_bf16x2(x - __uint_as_float(__builtin_amdgcn_perm(0u, hi, 0x01000c0cu)),
+                   y - __uint_as_float(hi & 0xffff0000u));
 }
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
@@ -628,9 +632,7 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
     float2* Pd = P + ((long long)t * q.NR + R) * slp;
     float2* Pm = P + ((long long)tm * q.NR + mR) * slp;
     {
-      f4 acc2[4][2];
-#pragma unroll
-      for (int Jt = 0; Jt < 4; ++Jt) acc2[Jt][0] = acc2[Jt][1] = f4{0, 0, 0, 0};
+      f4 acc2[4][2];  // step 0 starts them from an inline zero operand
 #pragma unroll
       for (int st = 0; st < 2; ++st) {
 #pragma unroll
@@ -648,7 +650,8 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
           for (int Jt = 0; Jt < 4; ++Jt) {
             const bf8 ah = *reinterpret_cast<const bf8*>(&Cbb[((0 * 2 + st) * kMP + 16 * Jt + li) * kCBB + 8 * lk]);
             const bf8 al = *reinterpret_cast<const bf8*>(&Cbb[((1 * 2 + st) * kMP + 16 * Jt + li) * kCBB + 8 * lk]);
-            acc2[Jt][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc2[Jt][pt], 0, 0, 0);
+            acc2[Jt][pt] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, st == 0 ? f4{0, 0, 0, 0} : acc2[Jt][pt], 0, 0, 0);
             acc2[Jt][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc2[Jt][pt], 0, 0, 0);
             acc2[Jt][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc2[Jt][pt], 0, 0, 0);
           }
@@ -1229,9 +1232,9 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
       const bool row_ok = r < q.mA && (!LIST || r < (mt & 0xffff));
       const float2 v0 = keep(wreg[u][0], row_ok && c0_ok && (!LIST || wc < (mt >> 16)));
       const float2 v1 = keep(wreg[u][1], row_ok && c1_ok && (!LIST || wc + 1 < (mt >> 16)));
-      const unsigned rh = pack_bf16x2(v0.x, v1.x), ih = pack_bf16x2(v0.y, v1.y);
-      const unsigned rl = pack_bf16x2(v0.x - __uint_as_float(rh << 16), v1.x - __uint_as_float(rh & 0xffff0000u));
-      const unsigned il = pack_bf16x2(v0.y - __uint_as_float(ih << 16), v1.y - __uint_as_float(ih & 0xffff0000u));
+      unsigned rh, rl, ih, il;
+      split_bf16x2(v0.x, v1.x, rh, rl);
+      split_bf16x2(v0.y, v1.y, ih, il);
       const int o = r * kWBS + wc;
       *reinterpret_cast<unsigned*>(&Wp[0 * kWBP + o]) = rh;
       *reinterpret_cast<unsigned*>(&Wp[1 * kWBP + o]) = rl;
@@ -1278,8 +1281,9 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     for (int m = 0; m < 3; ++m) {
       const bf8 ah = *reinterpret_cast<const bf8*>(&Cap[((0 * 2 + st) * kPL + 16 * m + li) * kCBS + 8 * lk]);
       const bf8 al = *reinterpret_cast<const bf8*>(&Cap[((1 * 2 + st) * kPL + 16 * m + li) * kCBS + 8 * lk]);
-      acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brh, acc2[m][0], 0, 0, 0);
-      acc2[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bih, acc2[m][1], 0, 0, 0);
+      // step 0 starts the accumulators from zero (an inline zero operand, no register fill)
+      acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brh, st == 0 ? f4{0, 0, 0, 0} : acc2[m][0], 0, 0, 0);
+      acc2[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bih, st == 0 ? f4{0, 0, 0, 0} : acc2[m][1], 0, 0, 0);
       acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, brl, acc2[m][0], 0, 0, 0);
       acc2[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bil, acc2[m][1], 0, 0, 0);
       acc2[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, brh, acc2[m][0], 0, 0, 0);
@@ -1316,9 +1320,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     }
     Blk nf = nn;
     blk_fill<LIST>(nf, q);
-    f4 acc2[3][2];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) acc2[m][0] = acc2[m][1] = f4{0, 0, 0, 0};
+    f4 acc2[3][2];  // set by the products (product wavefronts only)
     if (mm) {
       f4 zr0, zi0, zr1, zi1;
 #pragma unroll

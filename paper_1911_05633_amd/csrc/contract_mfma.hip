@@ -470,10 +470,57 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
+// Dense walk of the BF16-split polarizability in bands: kPBand consecutive atoms of A for each
+// atom of B, the A atom fastest, (tau, R) slowest.  Consecutive blocks of a band write the
+// two halves of the 128-byte lines that their mirror-block rows share, a block apart, so that
+// they mostly meet in L2 and reach HBM as whole lines (partial-line writes reach it far more
+// slowly); in counting order (B fastest) those halves are written 72 blocks apart.
+constexpr int kPBand = 4;
+__device__ __forceinline__ int band_size(int iA, const PairArgs& q) {
+  const int b0 = iA - iA % kPBand;
+  return q.cntA - b0 < kPBand ? q.cntA - b0 : kPBand;
+}
+__device__ __forceinline__ void bblk_start(Blk& k, long long b, const PairArgs& q) {
+  const long long per = (long long)q.cntA * q.cntB;
+  const long long tr = b / per;
+  const int r = (int)(b - tr * per);
+  k.R = (int)(tr % q.NR);
+  k.t = (int)(tr / q.NR);
+  const int full = q.cntA / kPBand, rem = q.cntA - kPBand * full;
+  if (r < full * kPBand * q.cntB) {
+    const int band = r / (kPBand * q.cntB), r2 = r - band * kPBand * q.cntB;
+    k.iB = r2 / kPBand;
+    k.iA = kPBand * band + (r2 - kPBand * k.iB);
+  } else {
+    const int r2 = r - full * kPBand * q.cntB;
+    k.iB = r2 / rem;
+    k.iA = kPBand * full + (r2 - rem * k.iB);
+  }
+}
+__device__ __forceinline__ void bblk_step(Blk& k, const PairArgs& q) {
+  const int bs = band_size(k.iA, q), a = k.iA % kPBand;
+  if (a + 1 < bs) {
+    ++k.iA;
+    return;
+  }
+  k.iA -= a;
+  if (++k.iB == q.cntB) {
+    k.iB = 0;
+    k.iA += bs;
+    if (k.iA == q.cntA) {
+      k.iA = 0;
+      if (++k.R == q.NR) {
+        k.R = 0;
+        ++k.t;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // polarizability on the BF16 matrix cores with split-precision products (GW_BF16X3),
-// for 9-orbital species with 49..64 product functions on both atoms.  Same blocks, walk,
-// G-tile prefetch and tau mirror as p_mfma.  Q is formed in FP32 and written split into
+// for 9-orbital species with 49..64 product functions on both atoms.  Same blocks, G-tile
+// prefetch and tau mirror as p_mfma; the dense walk goes in bands (above).  Q is formed in FP32 and written split into
 // bf16 hi / lo planes stored transposed, Q^T[p'][p] (row stride 72: the 16-byte A-operand
 // reads of eight lanes hit distinct banks).  GEMM1 (wavefront w, I tile w):
 // D1[p'][I] = sum_p Q[p][p'] C~_A[I][p] per part and per 16-row block pb of p', K = p in
@@ -558,13 +605,23 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
   Blk cur;
-  blk_start<LIST>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  // dense: band walk; block list: its contiguous range
+  auto adv = [&](Blk& x) {
+    if constexpr (LIST)
+      blk_step<true>(x, q);
+    else
+      bblk_step(x, q);
+  };
+  if constexpr (LIST)
+    blk_start<true>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  else
+    bblk_start(cur, bbeg < q.nblocks ? bbeg : 0, q);
   blk_fill<LIST>(cur, q);
   Blk nxt = cur, nn = cur;
-  blk_step<LIST>(nxt, q);
+  adv(nxt);
   blk_fill<LIST>(nxt, q);
-  blk_step<LIST>(nn, q);
-  blk_step<LIST>(nn, q);
+  adv(nn);
+  adv(nn);
   if (bbeg < bend) {
     fetch(cur);
     stage();
@@ -713,7 +770,7 @@ __global__ __launch_bounds__(256, 2) void p_bf16x3(const float2* __restrict__ GR
     if (more) stage();
     cur = nxt;
     nxt = nf;
-    blk_step<LIST>(nn, q);
+    adv(nn);
     __syncthreads();
   }
 }

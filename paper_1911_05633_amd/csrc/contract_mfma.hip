@@ -180,6 +180,55 @@ __device__ __forceinline__ void blk_fill(Blk& k, const PairArgs& q) {
   }
 }
 
+// Dense walk of the polarizability kernels in bands: kPBand consecutive atoms of A for each
+// atom of B, the A atom fastest, (tau, R) slowest.  Consecutive blocks of a band write the
+// two halves of the 128-byte lines that their mirror-block rows share, a block apart, so that
+// they mostly meet in L2 and reach HBM as whole lines (partial-line writes reach it far more
+// slowly); in counting order (B fastest) those halves are written 72 blocks apart.
+constexpr int kPBand = 4;
+__device__ __forceinline__ int band_size(int iA, const PairArgs& q) {
+  const int b0 = iA - iA % kPBand;
+  return q.cntA - b0 < kPBand ? q.cntA - b0 : kPBand;
+}
+template <class BK>  // Blk or GBlk (their t, R, iA, iB)
+__device__ __forceinline__ void bblk_start(BK& k, long long b, const PairArgs& q) {
+  const long long per = (long long)q.cntA * q.cntB;
+  const long long tr = b / per;
+  const int r = (int)(b - tr * per);
+  k.R = (int)(tr % q.NR);
+  k.t = (int)(tr / q.NR);
+  const int full = q.cntA / kPBand, rem = q.cntA - kPBand * full;
+  if (r < full * kPBand * q.cntB) {
+    const int band = r / (kPBand * q.cntB), r2 = r - band * kPBand * q.cntB;
+    k.iB = r2 / kPBand;
+    k.iA = kPBand * band + (r2 - kPBand * k.iB);
+  } else {
+    const int r2 = r - full * kPBand * q.cntB;
+    k.iB = r2 / rem;
+    k.iA = kPBand * full + (r2 - rem * k.iB);
+  }
+}
+template <class BK>
+__device__ __forceinline__ void bblk_step(BK& k, const PairArgs& q) {
+  const int bs = band_size(k.iA, q), a = k.iA % kPBand;
+  if (a + 1 < bs) {
+    ++k.iA;
+    return;
+  }
+  k.iA -= a;
+  if (++k.iB == q.cntB) {
+    k.iB = 0;
+    k.iA += bs;
+    if (k.iA == q.cntA) {
+      k.iA = 0;
+      if (++k.R == q.NR) {
+        k.R = 0;
+        ++k.t;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // polarizability
 // ---------------------------------------------------------------------------
@@ -264,13 +313,23 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
   Blk cur;
-  blk_start<LIST>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  // dense: band walk; block list: its contiguous range
+  auto adv = [&](Blk& x) {
+    if constexpr (LIST)
+      blk_step<true>(x, q);
+    else
+      bblk_step(x, q);
+  };
+  if constexpr (LIST)
+    blk_start<true>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  else
+    bblk_start(cur, bbeg < q.nblocks ? bbeg : 0, q);
   blk_fill<LIST>(cur, q);
   Blk nxt = cur, nn = cur;
-  blk_step<LIST>(nxt, q);
+  adv(nxt);
   blk_fill<LIST>(nxt, q);
-  blk_step<LIST>(nn, q);
-  blk_step<LIST>(nn, q);
+  adv(nn);
+  adv(nn);
   __syncthreads();  // minus-R table staged
   if (bbeg < bend) {
     fetch(cur);
@@ -439,7 +498,7 @@ __global__ __launch_bounds__(256, 2) void p_mfma(const CT* __restrict__ GR, CT* 
     if (more) stage();  // Xs, Ys were last read before the barrier above
     cur = nxt;
     nxt = nf;
-    blk_step<LIST>(nn, q);
+    adv(nn);
     __syncthreads();
   }
 }
@@ -468,53 +527,6 @@ __device__ __forceinline__ void split_bf16x2(float x, float y, unsigned& hi, uns
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
-}
-
-// Dense walk of the BF16-split polarizability in bands: kPBand consecutive atoms of A for each
-// atom of B, the A atom fastest, (tau, R) slowest.  Consecutive blocks of a band write the
-// two halves of the 128-byte lines that their mirror-block rows share, a block apart, so that
-// they mostly meet in L2 and reach HBM as whole lines (partial-line writes reach it far more
-// slowly); in counting order (B fastest) those halves are written 72 blocks apart.
-constexpr int kPBand = 4;
-__device__ __forceinline__ int band_size(int iA, const PairArgs& q) {
-  const int b0 = iA - iA % kPBand;
-  return q.cntA - b0 < kPBand ? q.cntA - b0 : kPBand;
-}
-__device__ __forceinline__ void bblk_start(Blk& k, long long b, const PairArgs& q) {
-  const long long per = (long long)q.cntA * q.cntB;
-  const long long tr = b / per;
-  const int r = (int)(b - tr * per);
-  k.R = (int)(tr % q.NR);
-  k.t = (int)(tr / q.NR);
-  const int full = q.cntA / kPBand, rem = q.cntA - kPBand * full;
-  if (r < full * kPBand * q.cntB) {
-    const int band = r / (kPBand * q.cntB), r2 = r - band * kPBand * q.cntB;
-    k.iB = r2 / kPBand;
-    k.iA = kPBand * band + (r2 - kPBand * k.iB);
-  } else {
-    const int r2 = r - full * kPBand * q.cntB;
-    k.iB = r2 / rem;
-    k.iA = kPBand * full + (r2 - rem * k.iB);
-  }
-}
-__device__ __forceinline__ void bblk_step(Blk& k, const PairArgs& q) {
-  const int bs = band_size(k.iA, q), a = k.iA % kPBand;
-  if (a + 1 < bs) {
-    ++k.iA;
-    return;
-  }
-  k.iA -= a;
-  if (++k.iB == q.cntB) {
-    k.iB = 0;
-    k.iA += bs;
-    if (k.iA == q.cntA) {
-      k.iA = 0;
-      if (++k.R == q.NR) {
-        k.R = 0;
-        ++k.t;
-      }
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1591,11 +1603,21 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
   const long long per = (q.nblocks + gridDim.x - 1) / gridDim.x;
   const long long bbeg = (long long)blockIdx.x * per;
   const long long bend = bbeg + per < q.nblocks ? bbeg + per : q.nblocks;
+  // dense: band walk; packed block list: its contiguous range
+  auto adv = [&](GBlk& x) {
+    if constexpr (PACK)
+      gblk_step<true>(x, q);
+    else
+      bblk_step(x, q);
+  };
   GBlk cur;
-  gblk_start<PACK>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  if constexpr (PACK)
+    gblk_start<true>(cur, bbeg < q.nblocks ? bbeg : 0, q);
+  else
+    bblk_start(cur, bbeg < q.nblocks ? bbeg : 0, q);
   gblk_fill<PACK>(cur, q);
   GBlk nxt = cur;
-  gblk_step<PACK>(nxt, q);
+  adv(nxt);
   __syncthreads();  // pair tables and the minus-R table staged
   if (bbeg < bend) {
     fetch(cur);
@@ -1707,7 +1729,7 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
     }
     if (more) stage();  // Xs, Ys were last read before the chunk loop's final barrier
     cur = nxt;
-    gblk_step<PACK>(nxt, q);
+    adv(nxt);
     __syncthreads();
   }
 }

@@ -1391,6 +1391,8 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     blk_fill<LIST>(nf, q);
     f4 acc2[3][2];  // set by the products (product wavefronts only)
     if (mm) {
+      // the product wavefronts issue ahead of staging and unfold work on their SIMD
+      __builtin_amdgcn_s_setprio(1);
       f4 zr0, zi0, zr1, zi1;
 #pragma unroll
       for (int st = 0; st < 2; ++st) {
@@ -1399,6 +1401,7 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
         gemm2(st, zr0, zi0, zr1, zi1, acc2);
         __builtin_amdgcn_sched_barrier(0);
       }
+      __builtin_amdgcn_s_setprio(0);
     }
     if (more) fetch(nxt, kWBU / 2, kWBU);
     __syncthreads();  // every wavefront is done with W

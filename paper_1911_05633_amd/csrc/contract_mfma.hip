@@ -531,10 +531,10 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 
 // ---------------------------------------------------------------------------
 // polarizability on the BF16 matrix cores with split-precision products (GW_BF16X3),
-// for 9-orbital species with 49..64 product functions on both atoms.  Same blocks, G-tile
-// prefetch and tau mirror as p_mfma; the dense walk goes in bands (above).  Q is formed in FP32 and written split into
-// bf16 hi / lo planes stored transposed, Q^T[p'][p] (row stride 72: the 16-byte A-operand
-// reads of eight lanes hit distinct banks).  GEMM1 (wavefront w, I tile w):
+// for 9-orbital species with 49..64 product functions on both atoms.  Same blocks, band walk,
+// G-tile prefetch and tau mirror as p_mfma.  Q is formed in FP32 and written split into bf16
+// hi / lo planes stored transposed, Q^T[p'][p] (row stride 72: the 16-byte A-operand reads of
+// eight lanes hit distinct banks).  GEMM1 (wavefront w, I tile w):
 // D1[p'][I] = sum_p Q[p][p'] C~_A[I][p] per part and per 16-row block pb of p', K = p in
 // two 32-deep steps (p >= 48 zero).  GEMM2: acc[J][I] += sum_p' C~_B[J][p'] D1[p'][I], its
 // K = p' taken in steps of two D1 blocks split in registers, K slot 8 g + e <->
@@ -1212,9 +1212,9 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3))) void s
 // tiles of B in the products, all four load and stage W (the next block's W is prefetched in
 // two halves, the second after this block's products) and share the orbital unfold (three
 // lanes per output, three of the nine rows a' each: X is staged as a zero-padded 9 x 9 tile,
-// so the unfold's 27 K and X reads per lane carry no branches and issue together).  The W block is split once when it is staged and
-// sits in LDS as four bf16 planes (re hi, re lo, im hi, im lo; row stride 72: the 16-byte
-// A-operand reads of eight lanes hit distinct banks).
+// so the unfold's 27 K and X reads per lane carry no branches and issue together).  The W
+// block is split once when it is staged and sits in LDS as four bf16 planes (re hi, re lo,
+// im hi, im lo; row stride 72: the 16-byte A-operand reads of eight lanes hit distinct banks).
 // GEMM1 (Z = W C~_B) takes K = 64 in two 32-deep steps.  GEMM2 (K = C~_A^T Z) takes
 // its K = 64 product functions I in two steps of two I tiles: the D fragments of GEMM1
 // for tiles 2s and 2s + 1 (rows 4 g + j in register j of lane group g) are split in

@@ -1422,24 +1422,24 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
       int pb[9];
 #pragma unroll
       for (int bp = 0; bp < 9; ++bp) pb[bp] = pair_index(bb, bp < q.nB ? bp : q.nB - 1, q.nB);
-      // lane third uh sums rows a' = 3 uh .. 3 uh + 2, each in FP32 (nine products, two
-      // interleaved partial sums each for re and im); the rows are accumulated in FP64: the
-      // split products carry about 2^-16 relative error, far above the FP32 rounding of a row
+      // lane third uh sums rows a' = 3 uh .. 3 uh + 2 (27 products) in FP32, two interleaved
+      // partial sums each for re and im, and the thirds meet in FP64: the split products carry
+      // about 2^-16 relative error, far above the FP32 rounding of a 27-term sum
+      float pr[2] = {0.f, 0.f}, pi[2] = {0.f, 0.f};
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const int ap = 3 * uh + i;
         const float2* Kr = Ks + pair_index(a, ap < q.nA ? ap : q.nA - 1, q.nA) * kKS;
         const float2* Xr = Xs + 9 * ap;
-        float pr[2] = {0.f, 0.f}, pi[2] = {0.f, 0.f};
 #pragma unroll
         for (int bp = 0; bp < 9; ++bp) {
           const float2 kv = Kr[pb[bp]], x = Xr[bp];
           pr[bp & 1] = fmaf(kv.x, x.x, fmaf(-kv.y, x.y, pr[bp & 1]));
           pi[bp & 1] = fmaf(kv.x, x.y, fmaf(kv.y, x.x, pi[bp & 1]));
         }
-        sr += (double)(pr[0] + pr[1]);
-        si += (double)(pi[0] + pi[1]);
       }
+      sr = (double)pr[0] + (double)pr[1];
+      si = (double)pi[0] + (double)pi[1];
     }
     // the three thirds meet in the first lane of the triple
     sr += __shfl_down(sr, 1) + __shfl_down(sr, 2);

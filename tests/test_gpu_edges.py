@@ -4,7 +4,9 @@ Shapes: one atom (4 orbitals, 16 product functions); a 1 x 1 x 1 mesh (one R, on
 one orbital and one product function per atom; the shortest tau grids (2 and 3 points, where
 the polarizability's tau mirror pairs the two end points, or leaves one self-mirrored middle
 point); and a 9-orbital species with 57 product functions (not a multiple of the 16-row
-matrix tiles), which the BF16 split kernels cover with a ragged last tile.  Each shape runs
+matrix tiles), which the BF16 split kernels cover with a ragged last tile; and seven 9-orbital
+atoms with 60 functions, whose polarizability walk takes one band of four A atoms and a short
+band of three (the dense P kernels walk bands of four).  Each shape runs
 k -> R and R -> k, P and Sigma in FP64, FP32 and BF16 split, the tau -> Matsubara transform
 and the fused drain with parity +1, -1 and 0, and the density.  Bars (max-abs error over
 max-abs of the oracle): 1e-12 FP64, 2e-6 FP32 products, 1e-5 BF16 split products.
@@ -43,6 +45,16 @@ def _si_m57():
                        config_id=23, request_id=3)
 
 
+def _si7_band():
+    lat = np.diag([7.1, 6.8, 6.5])
+    pos = np.array([[0.0, 0.0, 0.0], [1.4, 1.3, 1.5], [3.6, 0.4, 2.9], [5.2, 3.1, 0.8],
+                    [2.3, 4.7, 4.4], [0.6, 5.6, 2.2], [4.9, 5.3, 5.6]])
+    # 16 tau points of P times 4 R times 49 atom pairs: 3136 blocks, more than the grid of 2048
+    # workgroups, so that workgroups also step from block to block along the band walk
+    return sc.CellSpec("si7_band", lat, pos, np.zeros(7, dtype=np.int64), (9,), (60,), (2, 2, 1), 32, 30.0,
+                       config_id=24, request_id=7)
+
+
 SHAPES = {
     "one_atom": _one_atom,
     "mesh111": lambda: cells.tiny(mesh=(1, 1, 1), complex_hopping=True, request_id=4),
@@ -50,6 +62,7 @@ SHAPES = {
     "ntau2": lambda: cells.tiny(n_tau=2, beta=8.0, complex_hopping=True, request_id=5),
     "ntau3": lambda: cells.tiny(n_tau=3, beta=8.0, complex_hopping=True, request_id=6),
     "si_m57": _si_m57,
+    "si7_band": _si7_band,
 }
 _cache = {}
 

@@ -1227,7 +1227,10 @@ constexpr int kSBWaves = 4;                                   // wavefronts of t
 constexpr int kSBThreads = 64 * kSBWaves;
 constexpr int kWBU = kMP / (2 * kSBWaves);                    // W row steps per thread (two columns each)
 
-template <bool LIST>
+// W16: W rows start on 16-byte boundaries at every block column offset (every species has an
+// even number of product functions and W is 16-byte aligned), so a lane loads its column pair as
+// one 16-byte access
+template <bool LIST, bool W16>
 __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, const float2* __restrict__ WR,
                                               double2* __restrict__ S, const float* __restrict__ CpA,
                                               const float* __restrict__ CpB, const PairArgs q) {
@@ -1281,8 +1284,16 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
     for (int u = 0; u < kWBU; ++u)
       if (u >= u0 && u < u1) {
         const bool row_ok = 8 * u + 2 * w + wro < q.mA;
-        wreg[u][0] = ldraw(p + u * step, WR, row_ok && c0_ok);
-        wreg[u][1] = ldraw(p + u * step + 1, WR, row_ok && c1_ok);
+        if (W16) {
+          // m_B even: both columns of the pair are valid or neither is
+          const float4 v = ldraw(reinterpret_cast<const float4*>(p + u * step),
+                                 reinterpret_cast<const float4*>(WR), row_ok && c1_ok);
+          wreg[u][0] = make_float2(v.x, v.y);
+          wreg[u][1] = make_float2(v.z, v.w);
+        } else {
+          wreg[u][0] = ldraw(p + u * step, WR, row_ok && c0_ok);
+          wreg[u][1] = ldraw(p + u * step + 1, WR, row_ok && c1_ok);
+        }
       }
   };
   // X sits in LDS as a 9 x 9 tile, zero outside its n_A x n_B corner, so that the unfold runs
@@ -1459,15 +1470,17 @@ __device__ __forceinline__ void s_bf16x3_body(const float2* __restrict__ GR, con
 
 // Both walks ask for three wavefronts per SIMD (three workgroups per CU, 52.9 KB of LDS each):
 // the allocator fits them in 168 registers without spilling.
+template <bool W16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3(
     const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
     const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
-  s_bf16x3_body<false>(GR, WR, S, CpA, CpB, q);
+  s_bf16x3_body<false, W16>(GR, WR, S, CpA, CpB, q);
 }
+template <bool W16>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s_bf16x3_list(
     const float2* __restrict__ GR, const float2* __restrict__ WR, double2* __restrict__ S,
     const float* __restrict__ CpA, const float* __restrict__ CpB, const PairArgs q) {
-  s_bf16x3_body<true>(GR, WR, S, CpA, CpB, q);
+  s_bf16x3_body<true, W16>(GR, WR, S, CpA, CpB, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -1746,7 +1759,11 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
 // (Eq. (8) with C symmetric in its orbital pair).  M goes through LDS, L^T stays in registers
 // (the D fragment of its product is the B operand of the next), the chunk of W is staged in
 // LDS with row loads.  Wavefront w owns the orbitals a' = w and a' = w + 8 of atom A and keeps
-// one accumulator per a'; the sum over a' and over the wavefronts is taken in FP64.
+// one accumulator per a'; the sum over a' and over the wavefronts is taken in FP64.  With nine
+// orbitals on A the ninth a' would fall to wavefront 0 alone, doubling its products: in FP64 the
+// second slot then takes a' = 8 for the chunks ch with ch mod 8 = w on every wavefront instead
+// (an accumulator may mix a', whose contributions are summed anyway).  The FP32 products are
+// short enough that wavefront 0's extra share does not set the block's time.
 // ---------------------------------------------------------------------------
 template <class RT, class CT, bool PACK = false>
 __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, const CT* __restrict__ WR,
@@ -1768,8 +1785,11 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
   // I = 4 ks + lk and the two orbitals a' = w, w + 8 this wavefront owns.  Kept in registers for
   // FP32; FP64 reads it from the (cache-resident) table at each use, its registers being full.
   constexpr bool kRegC = sizeof(RT) == 4;
+  // second slot's a' (nine orbitals: a' = 8 on every wavefront, for its share of the chunks)
+  const bool rot9 = sizeof(RT) == 8 && nA == 9;
+  const int ap2 = rot9 ? 8 : w + 8;
   auto ca = [&](int ks, int u) -> RT {
-    const int I = 4 * ks + lk, ap = w + 8 * u;
+    const int I = 4 * ks + lk, ap = u == 0 ? w : ap2;
     return (ks < nKI && I < mA && li < nA && ap < nA) ? CA[((long long)I * nA + li) * nA + ap] : RT(0);
   };
   RT cav[2][kRegC ? kGKI : 1];
@@ -1883,8 +1903,8 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int ap = w + 8 * u;
-        if (ap < nA) {
+        const int ap = u == 0 ? w : ap2;
+        if (ap < nA && (u == 0 || !rot9 || (ch & 7) == w)) {
           // L^T[J][a] = sum_I W[I][J] C^I_{a a'}: A = W^T (row J = li, k = I), two chains
           typename M::acc lr = {0, 0, 0, 0}, lim = {0, 0, 0, 0};
           if constexpr (kRegC) {
@@ -1928,11 +1948,10 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
     for (int j = 0; j < 4; ++j) {
       double vr = 0.0, vi = 0.0;
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
-        if (w + 8 * u < nA) {
-          vr += (double)sr[u][j];
-          vi += (double)si[u][j];
-        }
+      for (int u = 0; u < 2; ++u) {  // a slot that took no a' holds zeros
+        vr += (double)sr[u][j];
+        vi += (double)si[u][j];
+      }
       Spart[w][li * 16 + M::drow(lk, j)] = make_double2(vr, vi);
     }
     __syncthreads();
@@ -1987,6 +2006,14 @@ PairArgs make_args(const gw_cell* c, const SpeciesDev& A, const SpeciesDev& B, i
   return q;
 }
 
+// Whether the BF16 self-energy may load W column pairs as 16-byte accesses (its W16)
+bool w_rows16(const gw_cell* c, const void* WR) {
+  if (reinterpret_cast<uintptr_t>(WR) & 15) return false;
+  for (const SpeciesDev& s : c->sp)
+    if (s.m & 1) return false;
+  return true;
+}
+
 unsigned grid_for(long long nblocks) { return (unsigned)(nblocks < 2048 ? nblocks : 2048); }
 
 }  // namespace
@@ -2037,8 +2064,8 @@ void launch_s_mfma_pair(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
     hipLaunchKernelGGL((s_mfma<double, double2>), dim3(grid_for(q.nblocks)), dim3(threads), 0, s,
                        (const double2*)GR, (const double2*)WR, (double2*)S, A.Cpair, B.Cpair, q);
   else if (p == GW_BF16X3 && A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)
-    hipLaunchKernelGGL(s_bf16x3, dim3(grid32), dim3(kSBThreads), 0, s, (const float2*)GR, (const float2*)WR,
-                       (double2*)S, A.Cpair32, B.Cpair32, q);
+    hipLaunchKernelGGL(w_rows16(c, WR) ? s_bf16x3<true> : s_bf16x3<false>, dim3(grid32), dim3(kSBThreads), 0, s,
+                       (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (A.m_pad == 64 && B.m_pad == 64 && A.np_pad == 48)  // n = 9 with m in (48, 64]: the Si-like species
     hipLaunchKernelGGL((s_mfma32<4, 16, 3>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
                        (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
@@ -2106,8 +2133,9 @@ bool launch_s_mfma_list(const gw_cell* c, const SpeciesDev& A, const SpeciesDev&
     hipLaunchKernelGGL((s_mfma<float, float2, true>), dim3(grid_for(q.nblocks)), dim3(kSThreads), 0, s,
                        (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);
   else if (p == GW_BF16X3 && si)
-    hipLaunchKernelGGL(s_bf16x3_list, dim3(grid32), dim3(kSBThreads), 0, s, (const float2*)GR, (const float2*)WR,
-                       (double2*)S, A.Cpair32, B.Cpair32, q);
+    hipLaunchKernelGGL(w_rows16(c, WR) ? s_bf16x3_list<true> : s_bf16x3_list<false>, dim3(grid32),
+                       dim3(kSBThreads), 0, s, (const float2*)GR, (const float2*)WR, (double2*)S, A.Cpair32,
+                       B.Cpair32, q);
   else if (si)
     hipLaunchKernelGGL((s_mfma32<4, 16, 3, true>), dim3(grid32), dim3(kS32Threads), 0, s, (const float2*)GR,
                        (const float2*)WR, (double2*)S, A.Cpair32, B.Cpair32, q);

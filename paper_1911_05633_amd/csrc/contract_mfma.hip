@@ -1760,10 +1760,9 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
 // (the D fragment of its product is the B operand of the next), the chunk of W is staged in
 // LDS with row loads.  Wavefront w owns the orbitals a' = w and a' = w + 8 of atom A and keeps
 // one accumulator per a'; the sum over a' and over the wavefronts is taken in FP64.  With nine
-// orbitals on A the ninth a' would fall to wavefront 0 alone, doubling its products: in FP64 the
-// second slot then takes a' = 8 for the chunks ch with ch mod 8 = w on every wavefront instead
-// (an accumulator may mix a', whose contributions are summed anyway).  The FP32 products are
-// short enough that wavefront 0's extra share does not set the block's time.
+// orbitals on A the ninth a' would fall to wavefront 0 alone, doubling its products: the second
+// slot then takes a' = 8 for the chunks ch with ch mod 8 = w on every wavefront instead (an
+// accumulator may mix a', whose contributions are summed anyway).
 // ---------------------------------------------------------------------------
 template <class RT, class CT, bool PACK = false>
 __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, const CT* __restrict__ WR,
@@ -1773,9 +1772,14 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
   typedef typename M::cplx CR;
   constexpr int kGKI = kGMP / 4;           // K steps over I at most
   constexpr int kWU = kGMP * 16 / kGThreads;  // W values of a chunk per thread
+  // FP32 keeps two slots of M and of the W chunk (chunk ch in slot ch & 1), so that one barrier
+  // per chunk separates its writes from its reads; FP64 (twice the bytes) keeps one slot and
+  // three barriers per chunk
+  constexpr bool kDB = sizeof(RT) == 4;
+  constexpr int kNB = kDB ? 2 : 1;
   __shared__ CR Xs[kMaxOrb * kMaxOrb];     // X[a'][b'], 16 x 16 zero padded
-  __shared__ CR Ms[16 * 16 * kGS];         // M[a'][J - 16 c][b] (row stride kGS)
-  __shared__ CR Wc[kGMP * kGS];            // W[I][J - 16 c]
+  __shared__ CR Ms[kNB][16 * 16 * kGS];    // M[a'][J - 16 c][b] (row stride kGS)
+  __shared__ CR Wc[kNB][kGMP * kGS];       // W[I][J - 16 c]
   __shared__ double2 Spart[kGThreads / 64][kMaxOrb * kMaxOrb];  // per-wavefront partial sums of S
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int nA = q.nA, nB = q.nB, mA = q.mA, mB = q.mB;
@@ -1786,7 +1790,7 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
   // FP32; FP64 reads it from the (cache-resident) table at each use, its registers being full.
   constexpr bool kRegC = sizeof(RT) == 4;
   // second slot's a' (nine orbitals: a' = 8 on every wavefront, for its share of the chunks)
-  const bool rot9 = sizeof(RT) == 8 && nA == 9;
+  const bool rot9 = nA == 9;
   const int ap2 = rot9 ? 8 : w + 8;
   auto ca = [&](int ks, int u) -> RT {
     const int I = 4 * ks + lk, ap = u == 0 ? w : ap2;
@@ -1825,13 +1829,13 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
     xr = ldraw(GR + ((long long)k.t * q.NR + k.R) * sl + (long long)(k.oa.y + a) * q.No + k.ob.y + c, GR,
                tid < 256 && a < nA && c < nB);
   };
-  auto store_w = [&](const GBlk& k, int ch) {
+  auto store_w = [&](const GBlk& k, int ch, int sb) {
     const int kA = k.mt & 0xffff, kB = k.mt >> 16, J0 = 16 * ch;
 #pragma unroll
     for (int u = 0; u < kWU; ++u) {
       const int i = tid + kGThreads * u, I = i >> 4, Jl = i & 15;
       const CT v = keep(wreg[u], I < kA && J0 + Jl < kB);
-      Wc[I * kGS + Jl] = mk<RT>((double)v.x, (double)v.y);
+      Wc[sb][I * kGS + Jl] = mk<RT>((double)v.x, (double)v.y);
     }
   };
   auto store_x = [&](const GBlk& k) {
@@ -1863,6 +1867,10 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
     load_w(cur, 0);
     load_x(cur);
   }
+  if constexpr (kDB) {  // the first block's X; later blocks' are staged at the previous block's end
+    if (bbeg < bend) store_x(cur);
+    __syncthreads();
+  }
   for (long long blk = bbeg; blk < bend; ++blk) {
     const GBlk k = cur;
     const bool more = blk + 1 < bend;
@@ -1874,10 +1882,14 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
     // W is zero beyond the block's functions: fewer chunks of J and K steps over I
     const int nChk = PACK ? (kB + 15) / 16 : nCh, nKIk = PACK ? (kA + 3) / 4 : nKI;
     for (int ch = 0; ch < nChk; ++ch) {
-      const int J0 = 16 * ch;
-      store_w(k, ch);
-      if (ch == 0) store_x(k);
-      __syncthreads();  // Xs (first chunk) and Wc staged; Ms free
+      const int J0 = 16 * ch, sb = kDB ? (ch & 1) : 0;
+      // Two slots: slot sb was last read by chunk ch - 2, before every wavefront passed chunk
+      // ch - 1's barrier (or, at ch < 2, before the previous block's closing barriers)
+      store_w(k, ch, sb);
+      if constexpr (!kDB) {
+        if (ch == 0) store_x(k);
+        __syncthreads();  // Xs (first chunk) and Wc staged; Ms free
+      }
       if (ch + 1 < nChk) {
         load_w(k, ch + 1);
       } else if (more) {
@@ -1898,9 +1910,10 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
           mi = M::op(x.y, cbr[h][ks], mi);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) Ms[(M::drow(lk, j) * 16 + Jl) * kGS + li] = mk<RT>((double)mr[j], (double)mi[j]);
+        for (int j = 0; j < 4; ++j)
+          Ms[sb][(M::drow(lk, j) * 16 + Jl) * kGS + li] = mk<RT>((double)mr[j], (double)mi[j]);
       }
-      __syncthreads();
+      __syncthreads();  // Ms and Wc of this chunk staged
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int ap = u == 0 ? w : ap2;
@@ -1911,14 +1924,14 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
 #pragma unroll
             for (int ks = 0; ks < kGKI; ++ks)
               if (ks < nKIk) {
-                const CR wv = Wc[(4 * ks + lk) * kGS + li];
+                const CR wv = Wc[sb][(4 * ks + lk) * kGS + li];
                 lr = M::op(wv.x, cav[u][ks], lr);
                 lim = M::op(wv.y, cav[u][ks], lim);
               }
           } else {
 #pragma unroll 2
             for (int ks = 0; ks < nKIk; ++ks) {
-              const CR wv = Wc[(4 * ks + lk) * kGS + li];
+              const CR wv = Wc[sb][(4 * ks + lk) * kGS + li];
               const RT cv = ca(ks, u);
               lr = M::op(wv.x, cv, lr);
               lim = M::op(wv.y, cv, lim);
@@ -1927,7 +1940,7 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
           // S^T[b][a] += sum_J M[a'][J][b] L^T[J][a]; step j: J = J0 + drow(lk, j)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const CR mv = Ms[(ap * 16 + M::drow(lk, j)) * kGS + li];
+            const CR mv = Ms[sb][(ap * 16 + M::drow(lk, j)) * kGS + li];
             sr[u] = M::op(mv.x, lr[j], sr[u]);
             sr[u] = M::op(-mv.y, lim[j], sr[u]);
             si[u] = M::op(mv.x, lim[j], si[u]);
@@ -1935,7 +1948,7 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
           }
         }
       }
-      __syncthreads();  // Wc and Ms are rewritten by the next chunk
+      if constexpr (!kDB) __syncthreads();  // Wc and Ms are rewritten by the next chunk
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -1953,6 +1966,11 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
         vi += (double)si[u][j];
       }
       Spart[w][li * 16 + M::drow(lk, j)] = make_double2(vr, vi);
+    }
+    // two slots: the next block's X, loaded with this block's last chunk (every wavefront is
+    // past that chunk's barrier, so no one reads Xs any more)
+    if constexpr (kDB) {
+      if (more) store_x(nxt);
     }
     __syncthreads();
     if (tid < 256) {

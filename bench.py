@@ -289,6 +289,8 @@ def time_path(g, spec, prec, steps, warmup, torch, log):
            for i, k in enumerate(KERNELS)}
     log(f"{prec}: {wall / steps * 1e3:.2f} ms/step; per-kernel ms: " +
         ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
+    log(f"{prec}: per step, P / Sigma / drain_P ms: " + "; ".join(
+        "/".join(f"{ev[s][i][0].elapsed_time(ev[s][i][1]):.2f}" for i in (1, 2, 3)) for s in range(steps)))
     return d, cell, wall / steps * 1e3, per
 
 

@@ -1688,17 +1688,26 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
       if (actk) {
         // GEMM1: A = Q^T (row p' = li, k = p), two chains (Re Q, Im Q)
         typename M::acc d1r = {0, 0, 0, 0}, d1i = {0, 0, 0, 0};
+        // four K steps per uniform branch, their reads issued together (n_KA is a multiple of 4)
 #pragma unroll
-        for (int ks = 0; ks < kGKA; ++ks)
-          if (ks < nKA) {
-            const CR qv = Qc[(4 * ks + lk) * kGS + li];
-            RT bv;
-            if constexpr (kRegB)
-              bv = b1[ks];
-            else
-              bv = CpArow[4 * ks];
-            d1r = M::op(qv.x, bv, d1r);
-            d1i = M::op(qv.y, bv, d1i);
+        for (int g = 0; g < kGKA / 4; ++g)
+          if (4 * g < nKA) {
+            CR qv[4];
+            RT bv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int ks = 4 * g + e;
+              qv[e] = Qc[(4 * ks + lk) * kGS + li];
+              if constexpr (kRegB)
+                bv[e] = b1[ks];
+              else
+                bv[e] = CpArow[4 * ks];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              d1r = M::op(qv[e].x, bv[e], d1r);
+              d1i = M::op(qv[e].y, bv[e], d1i);
+            }
           }
         // GEMM2: K = p' of the chunk, step j takes row drow(lk, j) of D1 (register j)
 #pragma unroll
@@ -1921,20 +1930,35 @@ __global__ __launch_bounds__(512) void s_mfma_gen(const CT* __restrict__ GR, con
           // L^T[J][a] = sum_I W[I][J] C^I_{a a'}: A = W^T (row J = li, k = I), two chains
           typename M::acc lr = {0, 0, 0, 0}, lim = {0, 0, 0, 0};
           if constexpr (kRegC) {
+            // four K steps per uniform branch, their W reads issued together (one LDS wait per
+            // group instead of one per step); rows past the block's functions are zero in Wc
 #pragma unroll
-            for (int ks = 0; ks < kGKI; ++ks)
-              if (ks < nKIk) {
-                const CR wv = Wc[sb][(4 * ks + lk) * kGS + li];
-                lr = M::op(wv.x, cav[u][ks], lr);
-                lim = M::op(wv.y, cav[u][ks], lim);
+            for (int g = 0; g < kGKI / 4; ++g)
+              if (4 * g < nKIk) {
+                CR wv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) wv[e] = Wc[sb][(4 * (4 * g + e) + lk) * kGS + li];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  lr = M::op(wv[e].x, cav[u][4 * g + e], lr);
+                  lim = M::op(wv[e].y, cav[u][4 * g + e], lim);
+                }
               }
           } else {
-#pragma unroll 2
-            for (int ks = 0; ks < nKIk; ++ks) {
-              const CR wv = Wc[sb][(4 * ks + lk) * kGS + li];
-              const RT cv = ca(ks, u);
-              lr = M::op(wv.x, cv, lr);
-              lim = M::op(wv.y, cv, lim);
+            // the same groups of four, with C read from the table (zero past its rows)
+            for (int g = 0; 4 * g < nKIk; ++g) {
+              CR wv[4];
+              RT cv[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                wv[e] = Wc[sb][(4 * (4 * g + e) + lk) * kGS + li];
+                cv[e] = ca(4 * g + e, u);
+              }
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                lr = M::op(wv[e].x, cv[e], lr);
+                lim = M::op(wv[e].y, cv[e], lim);
+              }
             }
           }
           // S^T[b][a] += sum_J M[a'][J][b] L^T[J][a]; step j: J = J0 + drow(lk, j)

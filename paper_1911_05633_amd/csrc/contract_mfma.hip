@@ -1709,16 +1709,20 @@ __global__ __launch_bounds__(512) void p_mfma_gen(const CT* __restrict__ GR, CT*
               d1i = M::op(qv[e].y, bv[e], d1i);
             }
           }
-        // GEMM2: K = p' of the chunk, step j takes row drow(lk, j) of D1 (register j)
+        // GEMM2: K = p' of the chunk, step j takes row drow(lk, j) of D1 (register j); one
+        // branch per J tile, its four C~_B reads issued together
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int Jt = 0; Jt < kGJT; ++Jt)
+          if (Jt < nJTk) {
+            RT a[4];
 #pragma unroll
-          for (int Jt = 0; Jt < kGJT; ++Jt)
-            if (Jt < nJTk) {
-              const RT a = Cb[(16 * Jt + li) * kGS + M::drow(lk, j)];
-              acc[Jt][0] = M::op(a, d1r[j], acc[Jt][0]);
-              acc[Jt][1] = M::op(a, d1i[j], acc[Jt][1]);
+            for (int j = 0; j < 4; ++j) a[j] = Cb[(16 * Jt + li) * kGS + M::drow(lk, j)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              acc[Jt][0] = M::op(a[j], d1r[j], acc[Jt][0]);
+              acc[Jt][1] = M::op(a[j], d1i[j], acc[Jt][1]);
             }
+          }
       }
       __syncthreads();  // Qc and Cb are rewritten by the next chunk
     }

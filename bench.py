@@ -20,6 +20,7 @@ on the same inputs, each with its error on the oracle's sample.  One JSON line i
 sample, whose outputs also give the error of the timed path.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -274,17 +275,28 @@ def time_path(g, spec, prec, steps, warmup, torch, log):
     """Build the inputs for one precision, time `steps` steps; returns (d, cell, ms, per-kernel ms)."""
     d = build_inputs(spec, prec, torch, log)
     cell = g.Cell.from_spec(spec, d["C"])
-    for _ in range(warmup):
-        run_step(g, cell, d, spec, prec)
-    torch.cuda.synchronize()
     ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in KERNELS]
           for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(steps):
-        run_step(g, cell, d, spec, prec, ev[s])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # torch creates an event at its first record: do that before the warm-up
+    for row in ev:
+        for pair in row:
+            for e in pair:
+                e.record()
+    # no garbage-collector pause while launches are queued (one can leave the GPU idle), and
+    # none between the warm-up and the timed steps
+    gc.collect()
+    gc.disable()
+    try:
+        for _ in range(warmup):
+            run_step(g, cell, d, spec, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            run_step(g, cell, d, spec, prec, ev[s])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gc.enable()
     per = {k: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(steps)]))
            for i, k in enumerate(KERNELS)}
     log(f"{prec}: {wall / steps * 1e3:.2f} ms/step; per-kernel ms: " +
@@ -857,7 +869,7 @@ def main():
     if args.prec == "fp64":
         others = []
     for alt in others:
-        da, cella, msa, pera = time_path(g, spec, alt, max(1, min(args.steps, 3)), 1, torch, log)
+        da, cella, msa, pera = time_path(g, spec, alt, max(1, min(args.steps, 3)), 2, torch, log)
         out["config"][f"{alt}_ms_per_step"] = msa
         out["config"][f"{alt}_per_kernel_ms"] = pera
         out["config"][f"speedup_vs_{alt}"] = msa / ms

@@ -9,7 +9,9 @@ atoms with 60 functions, whose polarizability walk takes one band of four A atom
 band of three (the dense P kernels walk bands of four).  Each shape runs
 k -> R and R -> k, P and Sigma in FP64, FP32 and BF16 split, the tau -> Matsubara transform
 and the fused drain with parity +1, -1 and 0, and the density.  Bars (max-abs error over
-max-abs of the oracle): 1e-12 FP64, 2e-6 FP32 products, 1e-5 BF16 split products.
+max-abs of the oracle): 1e-12 FP64, 2e-6 FP32 products, 1e-5 BF16 split products.  One more
+case runs the BF16 split self-energy on a W that starts 8 bytes into its allocation (the
+kernel's 8-byte load path) against the same W 16-byte aligned.
 """
 import numpy as np
 import pytest
@@ -138,6 +140,34 @@ def test_edge_contractions(name, prec):
     eP, eS = relmax(Ph, d["PR"]), relmax(Sh, SR)
     print(f"[edge P/Sigma] {name} {prec}: P {eP:.2e}, Sigma {eS:.2e}", flush=True)
     assert eP < tol and eS < tol
+
+
+def test_sigma_bf16_w_alignment():
+    """The BF16 split self-energy loads each lane's pair of W columns as one 16-byte access
+    only when every species has an even number of product functions and W is 16-byte aligned;
+    a W that starts 8 bytes into its allocation takes the two 8-byte loads.  Both give the
+    same bits, within the BF16 split bar of the oracle."""
+    import torch
+    import paper_1911_05633_amd as g
+    d = _case("si7_band")
+    spec = d["spec"]
+    print("[edge Sigma W alignment] si7_band bf16x3", flush=True)
+    cell = g.Cell.from_spec(spec, d["C"])
+    GR = dev(d["GR"], torch.complex64)
+    WR = dev(d["WR"], torch.complex64)
+    buf = torch.empty(WR.numel() + 1, dtype=torch.complex64, device="cuda")
+    WR8 = buf[1:].view(WR.shape)
+    WR8.copy_(WR)
+    assert WR.data_ptr() % 16 == 0 and WR8.data_ptr() % 16 == 8
+    out = []
+    for W in (WR, WR8):
+        S = torch.full((spec.n_tau, spec.N_R, spec.N_orb, spec.N_orb), float("nan"), dtype=torch.complex128,
+                       device="cuda")
+        g.gw_self_energy(cell, GR, W, S, prec="bf16x3")
+        out.append(host(S))
+    assert np.array_equal(out[0], out[1])
+    SR = oracle.self_energy_r(d["GR"], d["WR"].astype(np.complex64).astype(np.complex128), spec, d["C"])
+    assert relmax(out[0], SR) < 1e-5
 
 
 @pytest.mark.parametrize("name", list(SHAPES))
